@@ -1,0 +1,153 @@
+/*
+ * mpdp.h -- C-ABI of the MI355X (gfx950) MPDP join-order optimizer.
+ *
+ * MPDP (arXiv 2202.13511) finds the cheapest cross-product-free bushy join
+ * tree of a query by a dynamic program over connected relation subsets,
+ * level by level in subset size (Section 5, Alg. 5): for every size k it
+ * unranks the k-subsets, filters the connected ones, enumerates their valid
+ * join pairs (csg-cmp pairs, Section 2.1) with the block-based enumeration of
+ * Section 3.2 (Alg. 3; Alg. 2 when the join graph is a tree), costs every
+ * pair, keeps the best pair per subset and writes it to the memo.  All of
+ * that runs as HIP kernels on one GPU; the host only validates the input,
+ * uploads a few kilobytes of query information and reads back the plan.
+ *
+ * Query information (QI of Alg. 1 / Alg. 5): relations 0..n-1, one edge per
+ * join predicate, base cardinalities and edge selectivities.
+ *
+ * Shared definitions (the paper leaves estimation and cost formulas open,
+ * Section 6.1; these are this library's):
+ *   card(S)  c = 1.0; for v in S ascending { c = c*card[v]; for u in S,
+ *            u < v, (u,v) an edge, ascending: c = c*sel(u,v) };
+ *            card(S) = (c < 1.0) ? 1.0 : c.  Evaluated in IEEE binary64,
+ *            left to right, no fused multiply-add.
+ *   C_out    cost({v}) = 0; cost(L join R) = (cost(L) + cost(R)) + card(L u R).
+ *   PG-like  cost({v}) = 0.01*card[v];
+ *            HJ = (((cL + cR) + 0.0125*card(R)) + 0.0025*card(L)) + 0.01*card(S)
+ *            NL = ((cL + cR) + (0.0025*card(L))*card(R)) + 0.01*card(S)
+ *            (PostgreSQL's default cpu_tuple_cost 0.01 and
+ *            cpu_operator_cost 0.0025; R is the hashed / inner side).
+ *   Best plan of S: the smallest key (cost, left relation bitmap, op) over
+ *            all candidates, with HASH < NESTLOOP.  The result is independent
+ *            of enumeration order and launch configuration.
+ *
+ * Bitmaps: bit v of a uint32_t stands for relation v (n <= 32).
+ */
+#ifndef MPDP_H
+#define MPDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPDP_OK = 0,
+    MPDP_EINVAL = 1,         /* malformed input or null required pointer           */
+    MPDP_ENOTCONNECTED = 2,  /* join graph disconnected: no cross-product-free plan */
+    MPDP_ETOOLARGE = 3,      /* n > 32: beyond the bitmap width of the exact DP    */
+    MPDP_ENOMEM = 4,         /* workspace too small, or device allocation failed   */
+    MPDP_EDEVICE = 5         /* a HIP runtime error                                */
+} mpdp_status;
+
+typedef enum { MPDP_COST_COUT = 0, MPDP_COST_PGLIKE = 1 } mpdp_cost_model;
+
+typedef enum {
+    MPDP_OP_SCAN = 0,      /* base relation                         */
+    MPDP_OP_HASH = 1,      /* hash join (PG-like)                   */
+    MPDP_OP_NESTLOOP = 2,  /* nested-loop join (PG-like)            */
+    MPDP_OP_JOIN = 3       /* logical join (C_out has no operator)  */
+} mpdp_op;
+
+/* One join predicate between relations u and v (0-based, u != v). */
+typedef struct { uint32_t u, v; } mpdp_edge;
+
+/* One node of the plan tree (Section 5: the best plan is rebuilt from the
+ * memo by following left/right).  plan_out holds 2n-1 nodes: nodes 0..n-1 are
+ * the base relations in index order, join nodes follow in post-order (left
+ * subtree, right subtree, node) and the root is node 2n-2. */
+typedef struct {
+    int32_t left, right;   /* child node index, -1 for a base relation     */
+    uint32_t relset;       /* relations under this node                     */
+    uint32_t op;           /* mpdp_op                                       */
+    double cost;           /* cost of the subplan                           */
+    double card;           /* card(relset)                                  */
+} mpdp_plan_node;
+
+/* Counters (Section 2.1 / Alg. 1 counters, with explicit conventions). */
+typedef struct {
+    uint64_t candidates;       /* subsets unranked: sum over k >= 2 of C(n,k)                 */
+    uint64_t connected_sets;   /* connected subsets with >= 2 relations                       */
+    uint64_t evaluated_pairs;  /* Alg. 3 EvaluatedCounter: sum over sets and blocks of 2^b - 2 */
+    uint64_t ccp_pairs;        /* csg-cmp pairs, unordered ((L,R) and (R,L) count once)        */
+    double ms_total;           /* host wall time of the call                                  */
+    double ms_filter;          /* device time of the unrank/filter kernels (MPDP_FLAG_TIMING) */
+    double ms_eval;            /* device time of the evaluate kernels      (MPDP_FLAG_TIMING) */
+    uint32_t levels;           /* number of DP levels run (n - 1)                             */
+    uint32_t eval_launches;    /* evaluate-kernel launches                                    */
+} mpdp_stats;
+
+/* Flags for mpdp_optimize_ws. */
+#define MPDP_FLAG_TIMING 1u   /* time the filter and evaluate kernels with HIP events */
+
+/* Status string for an mpdp_status value (static storage, never NULL). */
+const char *mpdp_status_str(mpdp_status s);
+
+/* Bytes of device workspace mpdp_optimize_ws needs for n relations
+ * (0 if n is 0 or above 32).  The memo is dense, indexed by the set bitmap:
+ * about 21 * 2^n bytes plus one level of candidate sets. */
+size_t mpdp_workspace_bytes(uint32_t n, mpdp_cost_model cost_model);
+
+/* Byte offsets of the memo arrays inside the workspace, for callers that
+ * inspect the memo after a successful call: cost (double[2^n]), card
+ * (double[2^n]), left (uint32_t[2^n]: left input relation set of the best
+ * join, 0 for base relations and unconnected sets), op (uint8_t[2^n]).
+ * Only entries of connected sets are defined.  Returns MPDP_EINVAL for n
+ * outside 1..32 or a null pointer. */
+mpdp_status mpdp_memo_layout(uint32_t n, size_t *off_cost, size_t *off_card, size_t *off_left,
+                             size_t *off_op);
+
+/*
+ * Optimize one query on the current HIP device.
+ *   n, m          relations and edges (m may be 0 only when n == 1)
+ *   edges         host, m entries; no self loops, no duplicate pairs
+ *   cardinalities host, n finite values >= 1
+ *   selectivities host, m finite values in (0, 1], one per edge
+ *   cost_model    MPDP_COST_COUT or MPDP_COST_PGLIKE
+ *   plan_out      host, caller-allocated, 2n-1 nodes (layout above)
+ *   cost_out      host, receives the root cost
+ *   stats_out     host, optional (NULL to skip)
+ * The library allocates and frees its own workspace and uses the null
+ * stream; it keeps no pointer after returning.  Outputs are written only on
+ * MPDP_OK.  Validation happens on the host before any HIP call, so every
+ * error except MPDP_ENOMEM / MPDP_EDEVICE is reported without a GPU.
+ */
+mpdp_status mpdp_optimize(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                          const double *cardinalities, const double *selectivities,
+                          mpdp_cost_model cost_model, mpdp_plan_node *plan_out,
+                          double *cost_out, mpdp_stats *stats_out);
+
+/*
+ * As mpdp_optimize, with caller-owned device memory and stream:
+ *   d_workspace   device pointer to at least mpdp_workspace_bytes(n, cost_model)
+ *                 bytes, 256-byte aligned; contents on entry are ignored
+ *   ws_bytes      its size (MPDP_ENOMEM if too small)
+ *   hip_stream    hipStream_t to enqueue on (NULL: the null stream)
+ *   flags         0 or MPDP_FLAG_TIMING
+ * All kernels run on hip_stream; the call waits for that stream before it
+ * returns because the plan is delivered to host memory.  Concurrent calls
+ * must use distinct workspaces.  After MPDP_OK the memo stays readable in the
+ * workspace (mpdp_memo_layout).
+ */
+mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                             const double *cardinalities, const double *selectivities,
+                             mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes,
+                             void *hip_stream, uint32_t flags, mpdp_plan_node *plan_out,
+                             double *cost_out, mpdp_stats *stats_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPDP_H */

@@ -1,0 +1,341 @@
+// Host side of the C-ABI in include/mpdp.h: input validation, the query
+// information upload, the level loop of Alg. 5 (unrank+filter, evaluate per
+// level, all enqueued on one stream with no host round trip between levels)
+// and the plan readback.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mpdp.h"
+#include "mpdp_internal.h"
+
+namespace {
+
+using mpdp::Counters;
+using mpdp::DevGraph;
+using mpdp::MemoPtrs;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+uint64_t binom64(uint32_t a, uint32_t b) {
+    if (b > a) return 0;
+    uint64_t r = 1;
+    for (uint32_t i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return r;
+}
+
+struct Layout {
+    size_t cost, card, left, op, list, graph, counters, plan, root, total;
+};
+
+Layout make_layout(uint32_t n) {
+    const size_t N = size_t(1) << n;
+    Layout L{};
+    size_t o = 0;
+    L.cost = o;     o = align_up(o + 8 * N);
+    L.card = o;     o = align_up(o + 8 * N);
+    L.left = o;     o = align_up(o + 4 * N);
+    L.op = o;       o = align_up(o + N);
+    L.list = o;     o = align_up(o + 4 * binom64(n, n / 2));
+    L.graph = o;    o = align_up(o + sizeof(DevGraph));
+    L.counters = o; o = align_up(o + sizeof(Counters));
+    L.plan = o;     o = align_up(o + sizeof(mpdp_plan_node) * 64);
+    L.root = o;     o = align_up(o + sizeof(double));
+    L.total = o;
+    return L;
+}
+
+struct Query {
+    uint32_t n, m;
+    int cost_model;
+    bool is_tree;
+    DevGraph g;
+};
+
+// Validation runs entirely on the host, before any HIP call.
+mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *card, const double *sel,
+                     mpdp_cost_model cm, Query &q) {
+    if (n == 0) return MPDP_EINVAL;
+    if (n > 32) return MPDP_ETOOLARGE;
+    if (cm != MPDP_COST_COUT && cm != MPDP_COST_PGLIKE) return MPDP_EINVAL;
+    if (!card || (m > 0 && (!edges || !sel))) return MPDP_EINVAL;
+    if (m > n * (n - 1) / 2) return MPDP_EINVAL;
+    std::memset(&q, 0, sizeof(q));
+    q.n = n;
+    q.m = m;
+    q.cost_model = cm;
+    DevGraph &g = q.g;
+    g.n = n;
+    g.m = m;
+    g.cost_model = (uint32_t)cm;
+    for (uint32_t v = 0; v < n; ++v) {
+        if (!std::isfinite(card[v]) || !(card[v] >= 1.0)) return MPDP_EINVAL;
+        g.card[v] = card[v];
+        g.base_cost[v] = (cm == MPDP_COST_PGLIKE) ? 0.01 * card[v] : 0.0;
+    }
+    for (uint32_t i = 0; i < m; ++i) {
+        const uint32_t u = edges[i].u, v = edges[i].v;
+        if (u >= n || v >= n || u == v) return MPDP_EINVAL;
+        if (g.adj[u] & (1u << v)) return MPDP_EINVAL;  // duplicate predicate
+        if (!std::isfinite(sel[i]) || !(sel[i] > 0.0) || !(sel[i] <= 1.0)) return MPDP_EINVAL;
+        g.adj[u] |= 1u << v;
+        g.adj[v] |= 1u << u;
+        g.sel[u * 32 + v] = sel[i];
+        g.sel[v * 32 + u] = sel[i];
+    }
+    // connectivity of the whole join graph (no cross products, Section 2.1.1)
+    const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    uint32_t seen = 1u, frontier = 1u;
+    while (frontier) {
+        uint32_t nb = 0;
+        for (uint32_t t = frontier; t; t &= t - 1) nb |= g.adj[__builtin_ctz(t)];
+        frontier = nb & full & ~seen;
+        seen |= frontier;
+    }
+    if (seen != full) return MPDP_ENOTCONNECTED;
+    q.is_tree = (m == n - 1);
+    g.is_tree = q.is_tree ? 1u : 0u;
+    // tree rooted at relation 0: parent bits and subtree sets, via BFS order
+    if (q.is_tree) {
+        int order[32], head = 0, tail = 0;
+        int parent[32];
+        for (int v = 0; v < 32; ++v) parent[v] = -1;
+        uint32_t vis = 1u;
+        order[tail++] = 0;
+        while (head < tail) {
+            const int v = order[head++];
+            for (uint32_t t = g.adj[v] & ~vis; t; t &= t - 1) {
+                const int c = __builtin_ctz(t);
+                parent[c] = v;
+                vis |= 1u << c;
+                order[tail++] = c;
+            }
+        }
+        for (uint32_t v = 0; v < n; ++v) {
+            g.tree_desc[v] = 1u << v;
+            g.tree_parent_bit[v] = parent[v] >= 0 ? (1u << parent[v]) : 0u;
+        }
+        for (int i = tail - 1; i > 0; --i) g.tree_desc[parent[order[i]]] |= g.tree_desc[order[i]];
+    }
+    for (int b = 0; b < 4; ++b)
+        for (uint32_t x = 0; x < 256; ++x) {
+            uint32_t u = 0;
+            for (int j = 0; j < 8; ++j)
+                if ((x >> j) & 1u) {
+                    const uint32_t v = 8u * b + j;
+                    if (v < n) u |= g.adj[v];
+                }
+            g.nbr_byte[b][x] = u;
+        }
+    for (uint32_t a = 0; a <= 32; ++a)
+        for (uint32_t b = 0; b <= 32; ++b) g.binom[a * 33 + b] = (uint32_t)binom64(a, b);
+    return MPDP_OK;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+mpdp_status leaf_only(const Query &q, mpdp_plan_node *plan, double *cost_out) {
+    plan[0] = mpdp_plan_node{-1, -1, 1u, MPDP_OP_SCAN, q.g.base_cost[0], q.g.card[0]};
+    *cost_out = q.g.base_cost[0];
+    return MPDP_OK;
+}
+
+#define HIPCHK(expr)                                \
+    do {                                            \
+        if ((expr) != hipSuccess) return MPDP_EDEVICE; \
+    } while (0)
+
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t make(size_t k) {
+        ev.resize(k, nullptr);
+        for (auto &e : ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) { e = nullptr; return r; }
+        }
+        return hipSuccess;
+    }
+};
+
+mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint32_t flags,
+                mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out, double t0,
+                bool force_general) {
+    const uint32_t n = q.n;
+    const Layout L = make_layout(n);
+    if (ws_bytes < L.total) return MPDP_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return MPDP_EINVAL;
+    char *base = static_cast<char *>(d_ws);
+    MemoPtrs memo{reinterpret_cast<double *>(base + L.cost), reinterpret_cast<double *>(base + L.card),
+                  reinterpret_cast<uint32_t *>(base + L.left), reinterpret_cast<uint8_t *>(base + L.op)};
+    uint32_t *list = reinterpret_cast<uint32_t *>(base + L.list);
+    DevGraph *dg = reinterpret_cast<DevGraph *>(base + L.graph);
+    Counters *cnt = reinterpret_cast<Counters *>(base + L.counters);
+    mpdp_plan_node *dplan = reinterpret_cast<mpdp_plan_node *>(base + L.plan);
+    double *droot = reinterpret_cast<double *>(base + L.root);
+
+    const bool timing = (flags & MPDP_FLAG_TIMING) != 0;
+    EventPool ev;
+    if (timing) HIPCHK(ev.make(4 * (size_t)n));
+
+    HIPCHK(hipMemcpyAsync(dg, &q.g, sizeof(DevGraph), hipMemcpyHostToDevice, s));
+    HIPCHK(mpdp::launch_init(dg, n, memo, cnt, s));
+    const bool general = force_general || !q.is_tree;
+    uint64_t candidates = 0;
+    uint32_t launches = 0;
+    for (uint32_t k = 2; k <= n; ++k) {
+        const uint64_t nc = binom64(n, k);
+        candidates += nc;
+        if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 8], s));
+        HIPCHK(mpdp::launch_filter(dg, k, nc, list, cnt, s));
+        if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 7], s));
+        if (general)
+            HIPCHK(mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, cnt, memo, s));
+        else
+            HIPCHK(mpdp::launch_eval_tree(dg, q.cost_model, k, nc, list, cnt, memo, s));
+        ++launches;
+        if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 6], s));
+    }
+    HIPCHK(mpdp::launch_extract(dg, n, memo, dplan, droot, cnt, s));
+    std::vector<mpdp_plan_node> plan(2 * n - 1);
+    Counters hc{};
+    double root = 0.0;
+    HIPCHK(hipMemcpyAsync(plan.data(), dplan, sizeof(mpdp_plan_node) * (2 * n - 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&root, droot, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc.extract_error) return MPDP_EDEVICE;
+
+    std::memcpy(plan_out, plan.data(), sizeof(mpdp_plan_node) * (2 * n - 1));
+    *cost_out = root;
+    if (stats_out) {
+        mpdp_stats st{};
+        st.candidates = candidates;
+        uint64_t conn = 0, tree_ccp = 0;
+        for (uint32_t k = 2; k <= n; ++k) {
+            conn += hc.level_count[k];
+            tree_ccp += (uint64_t)(k - 1) * hc.level_count[k];
+        }
+        st.connected_sets = conn;
+        if (general) {
+            st.ccp_pairs = hc.ccp;
+            st.evaluated_pairs = hc.evaluated;
+        } else {
+            st.ccp_pairs = tree_ccp;
+            st.evaluated_pairs = 2 * tree_ccp;
+        }
+        st.levels = n - 1;
+        st.eval_launches = launches;
+        if (timing) {
+            double f = 0.0, e = 0.0;
+            for (uint32_t k = 2; k <= n; ++k) {
+                float a = 0.f, b = 0.f;
+                HIPCHK(hipEventElapsedTime(&a, ev.ev[4 * k - 8], ev.ev[4 * k - 7]));
+                HIPCHK(hipEventElapsedTime(&b, ev.ev[4 * k - 7], ev.ev[4 * k - 6]));
+                f += a;
+                e += b;
+            }
+            st.ms_filter = f;
+            st.ms_eval = e;
+        }
+        st.ms_total = now_ms() - t0;
+        *stats_out = st;
+    }
+    return MPDP_OK;
+}
+
+// Internal flag for tests: run Alg. 3 (the general kernel) on tree joins too.
+constexpr uint32_t kFlagForceGeneral = 0x100u;
+
+}  // namespace
+
+extern "C" {
+
+const char *mpdp_status_str(mpdp_status s) {
+    switch (s) {
+        case MPDP_OK: return "ok";
+        case MPDP_EINVAL: return "invalid argument";
+        case MPDP_ENOTCONNECTED: return "join graph is not connected";
+        case MPDP_ETOOLARGE: return "more than 32 relations";
+        case MPDP_ENOMEM: return "workspace too small or device allocation failed";
+        case MPDP_EDEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+size_t mpdp_workspace_bytes(uint32_t n, mpdp_cost_model cost_model) {
+    (void)cost_model;
+    if (n == 0 || n > 32) return 0;
+    return make_layout(n).total;
+}
+
+mpdp_status mpdp_memo_layout(uint32_t n, size_t *off_cost, size_t *off_card, size_t *off_left, size_t *off_op) {
+    if (n == 0 || n > 32 || !off_cost || !off_card || !off_left || !off_op) return MPDP_EINVAL;
+    const Layout L = make_layout(n);
+    *off_cost = L.cost;
+    *off_card = L.card;
+    *off_left = L.left;
+    *off_op = L.op;
+    return MPDP_OK;
+}
+
+mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,
+                             const double *selectivities, mpdp_cost_model cost_model, void *d_workspace,
+                             size_t ws_bytes, void *hip_stream, uint32_t flags, mpdp_plan_node *plan_out,
+                             double *cost_out, mpdp_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!plan_out || !cost_out) return MPDP_EINVAL;
+    Query q;
+    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, q);
+    if (st != MPDP_OK) return st;
+    if (n == 1) {
+        st = leaf_only(q, plan_out, cost_out);
+        if (stats_out) {
+            std::memset(stats_out, 0, sizeof(*stats_out));
+            stats_out->ms_total = now_ms() - t0;
+        }
+        return st;
+    }
+    if (!d_workspace) return MPDP_EINVAL;
+    return run(q, d_workspace, ws_bytes, static_cast<hipStream_t>(hip_stream), flags, plan_out, cost_out,
+               stats_out, t0, (flags & kFlagForceGeneral) != 0);
+}
+
+mpdp_status mpdp_optimize(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,
+                          const double *selectivities, mpdp_cost_model cost_model, mpdp_plan_node *plan_out,
+                          double *cost_out, mpdp_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!plan_out || !cost_out) return MPDP_EINVAL;
+    Query q;
+    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, q);
+    if (st != MPDP_OK) return st;
+    if (n == 1) {
+        st = leaf_only(q, plan_out, cost_out);
+        if (stats_out) {
+            std::memset(stats_out, 0, sizeof(*stats_out));
+            stats_out->ms_total = now_ms() - t0;
+        }
+        return st;
+    }
+    const size_t bytes = make_layout(n).total;
+    void *ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess || !ws) {
+        (void)hipGetLastError();
+        return MPDP_ENOMEM;
+    }
+    st = run(q, ws, bytes, nullptr, 0, plan_out, cost_out, stats_out, t0, false);
+    if (hipFree(ws) != hipSuccess && st == MPDP_OK) st = MPDP_EDEVICE;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+"""Python binding of the C-ABI in include/mpdp.h (argument marshalling only).
+
+Every step of the optimizer runs in the HIP library ``libmpdp.so`` built from
+``csrc/``; this module converts arrays, calls the entry points with the same
+names, and turns the results into Python objects.  PyTorch is used only to
+own the device workspace and to name the stream.  If the library is missing
+the import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpdp.so")
+
+MPDP_OK, MPDP_EINVAL, MPDP_ENOTCONNECTED, MPDP_ETOOLARGE, MPDP_ENOMEM, MPDP_EDEVICE = range(6)
+MPDP_COST_COUT, MPDP_COST_PGLIKE = 0, 1
+MPDP_OP_SCAN, MPDP_OP_HASH, MPDP_OP_NESTLOOP, MPDP_OP_JOIN = 0, 1, 2, 3
+MPDP_FLAG_TIMING = 1
+_FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
+
+EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
+            "mpdp_optimize_ws"]
+
+
+class mpdp_edge(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_uint32), ("v", ctypes.c_uint32)]
+
+
+class mpdp_plan_node(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_int32), ("right", ctypes.c_int32), ("relset", ctypes.c_uint32),
+                ("op", ctypes.c_uint32), ("cost", ctypes.c_double), ("card", ctypes.c_double)]
+
+
+class mpdp_stats(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_uint64), ("connected_sets", ctypes.c_uint64),
+                ("evaluated_pairs", ctypes.c_uint64), ("ccp_pairs", ctypes.c_uint64),
+                ("ms_total", ctypes.c_double), ("ms_filter", ctypes.c_double),
+                ("ms_eval", ctypes.c_double), ("levels", ctypes.c_uint32),
+                ("eval_launches", ctypes.c_uint32)]
+
+
+class MpdpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mpdp status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmpdp.so and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2202_13511_amd.build.build()")
+    L = ctypes.CDLL(path)
+    u32, sz, vp = ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p
+    f64p = ctypes.POINTER(ctypes.c_double)
+    L.mpdp_status_str.argtypes = [ctypes.c_int]
+    L.mpdp_status_str.restype = ctypes.c_char_p
+    L.mpdp_workspace_bytes.argtypes = [u32, ctypes.c_int]
+    L.mpdp_workspace_bytes.restype = sz
+    L.mpdp_memo_layout.argtypes = [u32] + [ctypes.POINTER(sz)] * 4
+    L.mpdp_memo_layout.restype = ctypes.c_int
+    common = [u32, u32, ctypes.POINTER(mpdp_edge), f64p, f64p, ctypes.c_int]
+    outs = [ctypes.POINTER(mpdp_plan_node), f64p, ctypes.POINTER(mpdp_stats)]
+    L.mpdp_optimize.argtypes = common + outs
+    L.mpdp_optimize.restype = ctypes.c_int
+    L.mpdp_optimize_ws.argtypes = common + [vp, sz, vp, u32] + outs
+    L.mpdp_optimize_ws.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+@dataclass
+class Result:
+    cost: float
+    plan: list            # list of dicts, layout of mpdp_plan_node
+    stats: dict
+
+    def plan_array(self) -> np.ndarray:
+        return np.array([(p["left"], p["right"], p["relset"], p["op"], p["cost"], p["card"])
+                         for p in self.plan],
+                        dtype=[("left", "i4"), ("right", "i4"), ("relset", "u4"), ("op", "u4"),
+                               ("cost", "f8"), ("card", "f8")])
+
+
+def mpdp_status_str(status: int) -> str:
+    return load().mpdp_status_str(int(status)).decode()
+
+
+def mpdp_workspace_bytes(n: int, cost_model: int = MPDP_COST_COUT) -> int:
+    return int(load().mpdp_workspace_bytes(int(n), int(cost_model)))
+
+
+def mpdp_memo_layout(n: int) -> dict:
+    o = [ctypes.c_size_t() for _ in range(4)]
+    st = load().mpdp_memo_layout(int(n), *[ctypes.byref(x) for x in o])
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    return dict(cost=o[0].value, card=o[1].value, left=o[2].value, op=o[3].value)
+
+
+def _marshal(n, edges, card, sel):
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.uint32).reshape(-1, 2))
+    c = np.ascontiguousarray(np.asarray(card, dtype=np.float64))
+    s = np.ascontiguousarray(np.asarray(sel, dtype=np.float64))
+    m = e.shape[0]
+    ep = e.ctypes.data_as(ctypes.POINTER(mpdp_edge)) if m else None
+    cp = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if c.size else None
+    sp = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if s.size else None
+    return (e, c, s), m, ep, cp, sp
+
+
+def _result(n, plan, cost, stats) -> Result:
+    nodes = [dict(left=p.left, right=p.right, relset=p.relset, op=p.op, cost=p.cost, card=p.card)
+             for p in plan[: 2 * n - 1]]
+    st = {f: getattr(stats, f) for f, _ in mpdp_stats._fields_}
+    return Result(cost.value, nodes, st)
+
+
+def _args(query):
+    return query.n, query.edges, query.card, query.sel
+
+
+def mpdp_optimize(query, cost_model: int = MPDP_COST_COUT) -> Result:
+    """Self-contained call: the library allocates its own workspace."""
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    plan = (mpdp_plan_node * max(2 * n - 1, 1))()
+    cost = ctypes.c_double()
+    stats = mpdp_stats()
+    st = load().mpdp_optimize(int(n), m, ep, cp, sp, int(cost_model), plan, ctypes.byref(cost),
+                              ctypes.byref(stats))
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    return _result(n, plan, cost, stats)
+
+
+def workspace(n: int, cost_model: int = MPDP_COST_COUT, device="cuda"):
+    """A torch-owned device workspace for mpdp_optimize_ws."""
+    import torch
+    nbytes = mpdp_workspace_bytes(n, cost_model)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def mpdp_optimize_ws(query, cost_model: int, ws, stream=None, flags: int = 0) -> Result:
+    """Run on caller-owned device memory (a torch uint8 tensor) and stream."""
+    import torch
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    if stream is None:
+        stream = torch.cuda.current_stream(ws.device)
+    plan = (mpdp_plan_node * max(2 * n - 1, 1))()
+    cost = ctypes.c_double()
+    stats = mpdp_stats()
+    st = load().mpdp_optimize_ws(int(n), m, ep, cp, sp, int(cost_model), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel() * ws.element_size(), ctypes.c_void_p(stream.cuda_stream),
+                                 int(flags), plan, ctypes.byref(cost), ctypes.byref(stats))
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    return _result(n, plan, cost, stats)
+
+
+def memo_arrays(ws, n: int) -> dict:
+    """Host copies of the memo arrays left in a workspace by mpdp_optimize_ws."""
+    lay = mpdp_memo_layout(n)
+    N = 1 << n
+    raw = ws
+    out = {}
+    for name, dt, width in (("cost", np.float64, 8), ("card", np.float64, 8), ("left", np.uint32, 4),
+                            ("op", np.uint8, 1)):
+        seg = raw[lay[name]: lay[name] + N * width].cpu().numpy()
+        out[name] = seg.view(dt)
+    return out

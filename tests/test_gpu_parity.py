@@ -1,0 +1,123 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, bit for
+bit, on every memo entry of small queries that still span several levels,
+both kernels (Alg. 2 tree kernel and Alg. 3 block kernel) and both cost
+models, plus edge cases (two relations, ties, the largest bitmap width)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.special import chain_interval_dp
+from paper_2202_13511_amd import mpdp, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CMS = [mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE]
+
+
+def run_ws(q, cm, flags=0):
+    import torch
+    ws = mpdp.workspace(q.n, cm, "cuda")
+    res = mpdp.mpdp_optimize_ws(q, cm, ws, flags=flags)
+    torch.cuda.synchronize()
+    return res, mpdp.memo_arrays(ws, q.n)
+
+
+def check_memo(q, gm, ref):
+    mask = ref.has_plan()
+    for name in ("cost", "card"):
+        a = gm[name][mask].view(np.uint64)
+        b = getattr(ref, name)[mask].view(np.uint64)
+        bad = np.nonzero(a != b)[0]
+        assert bad.size == 0, (q.name, name, np.nonzero(mask)[0][bad[:5]])
+    assert np.array_equal(gm["left"][mask], ref.left[mask]), q.name
+    assert np.array_equal(gm["op"][mask], ref.op[mask]), q.name
+
+
+def check_plan(q, res, ref):
+    want = oracle.plan_from_memo(ref)
+    assert len(res.plan) == len(want)
+    for a, b in zip(res.plan, want):
+        assert (a["relset"], a["left"], a["right"], a["op"]) == (b["relset"], b["left"], b["right"], b["op"])
+        assert np.float64(a["cost"]).view(np.uint64) == np.float64(b["cost"]).view(np.uint64)
+        assert np.float64(a["card"]).view(np.uint64) == np.float64(b["card"]).view(np.uint64)
+    assert np.float64(res.cost).view(np.uint64) == np.float64(ref.root_cost).view(np.uint64)
+
+
+def check_stats(q, res, ref, general):
+    st = res.stats
+    assert st["connected_sets"] == ref.connected_sets
+    assert st["ccp_pairs"] == ref.ccp_ordered // 2
+    assert st["candidates"] == (1 << q.n) - 1 - q.n
+    if general:
+        assert st["evaluated_pairs"] == oracle.mpdp(q, force_general=True).evaluated
+    else:
+        assert st["evaluated_pairs"] == ref.ccp_ordered
+
+
+def families():
+    qs = []
+    for s in range(2):
+        qs += [W.star(12, s), W.snowflake(14, s), W.random_tree(13, s), W.chain(12, s),
+               W.cycle(11, s), W.clique(9, s), W.random_connected(12, s, 0.2),
+               W.random_connected(11, 20 + s, 0.5), W.cycle_chords(s, n=13, chords=4)]
+    qs += [W.all_equal_clique(9), W.from_edges(2, [[0, 1]], 3, "pair")]
+    return qs
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_memo_parity_small(cm):
+    for q in families():
+        res, gm = run_ws(q, cm)
+        ref = oracle.mpdp(q, cm)
+        check_memo(q, gm, ref)
+        check_plan(q, res, ref)
+        tree = q.m == q.n - 1
+        check_stats(q, res, ref, general=not tree)
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_block_kernel_on_trees(cm):
+    """Alg. 3 kernel forced onto tree joins reaches the same memo."""
+    for q in [W.star(11, 4), W.snowflake(15, 5), W.random_tree(12, 6)]:
+        res, gm = run_ws(q, cm, flags=mpdp._FLAG_FORCE_GENERAL)
+        ref = oracle.mpdp(q, cm)
+        check_memo(q, gm, ref)
+        check_plan(q, res, ref)
+        check_stats(q, res, ref, general=True)
+
+
+def test_self_allocating_entry_point():
+    q = W.cycle_chords(7, n=12, chords=5)
+    res = mpdp.mpdp_optimize(q, mpdp.MPDP_COST_PGLIKE)
+    ref = oracle.mpdp(q, oracle.COST_PGLIKE)
+    check_plan(q, res, ref)
+
+
+def test_repeat_runs_identical():
+    """Tie storm: every split costs the same; results must not depend on
+    scheduling (three runs, same bits)."""
+    q = W.all_equal_clique(12)
+    outs = [run_ws(q, mpdp.MPDP_COST_COUT) for _ in range(3)]
+    for res, gm in outs[1:]:
+        for k in ("cost", "card", "left", "op"):
+            assert np.array_equal(gm[k], outs[0][1][k])
+    check_memo(q, outs[0][1], oracle.mpdp(q))
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_widest_bitmap_chain32(cm):
+    """n = 32 fills the 32-bit relation bitmap (2^32 - 33 candidates);
+    checked against the chain interval DP."""
+    q = W.chain(32, 11)
+    res = mpdp.mpdp_optimize(q, cm)
+    ref = chain_interval_dp(q, cm)
+    full = (1 << 32) - 1
+    c, k, L, op = ref[full]
+    assert res.cost == c
+    assert res.plan[-1]["relset"] == full and res.plan[-1]["op"] == op
+    assert res.plan[res.plan[-1]["left"]]["relset"] == L
+    for nd in res.plan[32:]:
+        S = nd["relset"]
+        c, k, L, op = ref[S]
+        assert nd["cost"] == c and nd["card"] == k and res.plan[nd["left"]]["relset"] == L
+    assert res.stats["connected_sets"] == 32 * 33 // 2 - 32
