@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark: MPDP exact join ordering on the 25-relation star (one GPU).
+
+A step optimizes a batch of 16 seeded 25-relation star queries (hub 0 plus
+24 leaves, card 10^U(2,8), sel U(0.1,1)/max card, C_out in binary64) end to
+end through the C-ABI (mpdp_optimize_ws): query upload, every DP level on
+the GPU, plan readback.  The query inputs are host arrays of a few hundred
+bytes; the memo lives in HBM.
+
+value      csg-cmp pairs (unordered) per second over the timed steps
+           (#ccp = 24 * 2^23 = 201,326,592 per query, fixed by the graph)
+roofline   the dominant kernel's algorithmic bytes over its HIP-event time
+cpu_baseline  the CPU oracle (MPDP in plain C, one thread) on one query
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ccp pairs evaluated/sec + optimize time (ms) 25-rel star; learned vs plain cost ratio"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_tree_star25.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2202_13511_amd", "csrc", "mpdp_kernels.hip")
+
+# Algorithmic bytes (per the memo layout: cost f64, card f64, left u32, op u8):
+#   per csg-cmp pair, C_out gathers the cost of the non-singleton side: 8 B
+#   per connected set, one memo entry is written: 21 B
+PAIR_BYTES_COUT = 8
+PAIR_BYTES_PGLIKE = 16
+SET_BYTES = 21
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic():
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--queries", type=int, default=16)
+    ap.add_argument("--n", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pglike", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the optimizer is a single-GPU program)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2202_13511_amd import mpdp, workloads
+
+    mpdp.load()  # fails loudly without the HIP library
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    queries = [workloads.star(n, s) for s in range(args.queries)]
+    ccp_per_query = (n - 1) * 2 ** (n - 2)
+
+    def run_batch(cm, ws, per_query_ms, kern):
+        total_ccp = 0
+        for q in queries:
+            t = time.perf_counter()
+            r = mpdp.mpdp_optimize_ws(q, cm, ws, flags=mpdp.MPDP_FLAG_TIMING)
+            per_query_ms.append((time.perf_counter() - t) * 1e3)
+            kern["eval_ms"] += r.stats["ms_eval"]
+            kern["filter_ms"] += r.stats["ms_filter"]
+            kern["eval_launches"] += r.stats["eval_launches"]
+            kern["sets"] += r.stats["connected_sets"]
+            kern["pairs"] += r.stats["ccp_pairs"]
+            if r.stats["ccp_pairs"] != ccp_per_query:
+                raise RuntimeError(f"{q.name}: {r.stats['ccp_pairs']} ccp, expected {ccp_per_query}")
+            total_ccp += r.stats["ccp_pairs"]
+        return total_ccp
+
+    def timed(cm, steps, warmup):
+        ws = mpdp.workspace(n, cm, dev)
+        for _ in range(warmup):
+            run_batch(cm, ws, [], dict(eval_ms=0.0, filter_ms=0.0, eval_launches=0, sets=0, pairs=0))
+        per_query = []
+        kern = dict(eval_ms=0.0, filter_ms=0.0, eval_launches=0, sets=0, pairs=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ccp = 0
+        for _ in range(steps):
+            ccp += run_batch(cm, ws, per_query, kern)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del ws
+        torch.cuda.empty_cache()
+        return ccp, dt, per_query, kern
+
+    ccp, dt, per_query, kern = timed(mpdp.MPDP_COST_COUT, args.steps, args.warmup)
+    value = ccp / dt
+    per_query.sort()
+    p50 = statistics.median(per_query)
+    p99 = per_query[min(len(per_query) - 1, int(round(0.99 * (len(per_query) - 1))))]
+
+    # roofline of the dominant kernel (the evaluate kernel), from HIP events
+    launches = max(kern["eval_launches"], 1)
+    alg_bytes = kern["pairs"] * PAIR_BYTES_COUT + kern["sets"] * SET_BYTES
+    eval_s = kern["eval_ms"] / 1e3
+    achieved = alg_bytes / eval_s / 1e9 if eval_s > 0 else 0.0
+    traffic = load_traffic()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ccp pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"star{n}: hub 0 + {n - 1} leaves, card 10^U(2,8), sel U(0.1,1)/max(card), "
+                        f"seeds 0..{args.queries - 1}, C_out, exact bushy DP",
+            "queries_per_step": args.queries,
+            "relations": n,
+            "cost_model": "C_out",
+            "ccp_per_query": ccp_per_query,
+        },
+        "optimize_ms_p50": p50,
+        "optimize_ms_p99": p99,
+        "kernel_ms_per_query": {
+            "eval": kern["eval_ms"] / len(per_query),
+            "filter": kern["filter_ms"] / len(per_query),
+        },
+        "roofline": {
+            "kernel": "k_eval_tree<C_out>",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes / launches,
+            "avg_launch_ms": kern["eval_ms"] / launches,
+        },
+    }
+
+    if not args.no_pglike:
+        ccp2, dt2, pq2, k2 = timed(mpdp.MPDP_COST_PGLIKE, max(1, args.steps // 5), 1)
+        pq2.sort()
+        out["pglike"] = {
+            "value": ccp2 / dt2,
+            "optimize_ms_p50": statistics.median(pq2),
+            "eval_ms_per_query": k2["eval_ms"] / len(pq2),
+            "eval_achieved_GBs": (k2["pairs"] * PAIR_BYTES_PGLIKE + k2["sets"] * SET_BYTES)
+                                 / (k2["eval_ms"] / 1e3) / 1e9 if k2["eval_ms"] > 0 else None,
+        }
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        a = torch.ones(nb, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nb
+
+    if not args.no_cpu_baseline:
+        import oracle
+        q = queries[0]
+        t = time.perf_counter()
+        m = oracle.mpdp(q, oracle.COST_COUT)
+        cdt = time.perf_counter() - t
+        gpu_root = mpdp.mpdp_optimize(q, mpdp.MPDP_COST_COUT).cost
+        out["cpu_baseline"] = {
+            "value": (m.ccp_ordered // 2) / cdt,
+            "unit": "ccp pairs/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{q.name}: one query of the batch, C_out, oracle MPDP (plain C, one thread), "
+                      f"{cdt:.1f} s",
+            "optimize_ms": cdt * 1e3,
+            "root_cost_bits_equal": bool(np.float64(gpu_root).view(np.uint64)
+                                         == np.float64(m.root_cost).view(np.uint64)),
+        }
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

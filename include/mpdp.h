@@ -95,16 +95,19 @@ typedef struct {
 const char *mpdp_status_str(mpdp_status s);
 
 /* Bytes of device workspace mpdp_optimize_ws needs for n relations
- * (0 if n is 0 or above 32).  The memo is dense, indexed by the set bitmap:
- * about 21 * 2^n bytes plus one level of candidate sets. */
+ * (0 if n is 0 or above 32): a memo entry of 21 bytes for every subset of
+ * the relations (2^n entries) plus one level of candidate sets. */
 size_t mpdp_workspace_bytes(uint32_t n, mpdp_cost_model cost_model);
 
 /* Byte offsets of the memo arrays inside the workspace, for callers that
  * inspect the memo after a successful call: cost (double[2^n]), card
  * (double[2^n]), left (uint32_t[2^n]: left input relation set of the best
- * join, 0 for base relations and unconnected sets), op (uint8_t[2^n]).
- * Only entries of connected sets are defined.  Returns MPDP_EINVAL for n
- * outside 1..32 or a null pointer. */
+ * join, 0 for base relations), op (uint8_t[2^n]).  The memo is
+ * level-compact: the entry of relation set S is at index
+ *     off(|S|) + colex(S),  off(k) = sum_{j<k} C(n, j),
+ *     colex(S) = sum over the members s_0 < s_1 < ... of C(s_i, i + 1),
+ * so each DP level is one contiguous slab.  Only entries of connected sets
+ * are defined.  Returns MPDP_EINVAL for n outside 1..32 or a null pointer. */
 mpdp_status mpdp_memo_layout(uint32_t n, size_t *off_cost, size_t *off_card, size_t *off_left,
                              size_t *off_op);
 

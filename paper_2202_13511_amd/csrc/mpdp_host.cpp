@@ -70,30 +70,31 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
     q.m = m;
     q.cost_model = cm;
     DevGraph &g = q.g;
+    mpdp::LdsImage &L = g.lds;
     g.n = n;
     g.m = m;
     g.cost_model = (uint32_t)cm;
     for (uint32_t v = 0; v < n; ++v) {
         if (!std::isfinite(card[v]) || !(card[v] >= 1.0)) return MPDP_EINVAL;
-        g.card[v] = card[v];
-        g.base_cost[v] = (cm == MPDP_COST_PGLIKE) ? 0.01 * card[v] : 0.0;
+        L.card[v] = card[v];
+        L.bcost[v] = (cm == MPDP_COST_PGLIKE) ? 0.01 * card[v] : 0.0;
     }
     for (uint32_t i = 0; i < m; ++i) {
         const uint32_t u = edges[i].u, v = edges[i].v;
         if (u >= n || v >= n || u == v) return MPDP_EINVAL;
-        if (g.adj[u] & (1u << v)) return MPDP_EINVAL;  // duplicate predicate
+        if (L.adj[u] & (1u << v)) return MPDP_EINVAL;  // duplicate predicate
         if (!std::isfinite(sel[i]) || !(sel[i] > 0.0) || !(sel[i] <= 1.0)) return MPDP_EINVAL;
-        g.adj[u] |= 1u << v;
-        g.adj[v] |= 1u << u;
-        g.sel[u * 32 + v] = sel[i];
-        g.sel[v * 32 + u] = sel[i];
+        L.adj[u] |= 1u << v;
+        L.adj[v] |= 1u << u;
+        g.sel_full[u * 32 + v] = sel[i];
+        g.sel_full[v * 32 + u] = sel[i];
     }
     // connectivity of the whole join graph (no cross products, Section 2.1.1)
     const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
     uint32_t seen = 1u, frontier = 1u;
     while (frontier) {
         uint32_t nb = 0;
-        for (uint32_t t = frontier; t; t &= t - 1) nb |= g.adj[__builtin_ctz(t)];
+        for (uint32_t t = frontier; t; t &= t - 1) nb |= L.adj[__builtin_ctz(t)];
         frontier = nb & full & ~seen;
         seen |= frontier;
     }
@@ -109,7 +110,7 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
         order[tail++] = 0;
         while (head < tail) {
             const int v = order[head++];
-            for (uint32_t t = g.adj[v] & ~vis; t; t &= t - 1) {
+            for (uint32_t t = L.adj[v] & ~vis; t; t &= t - 1) {
                 const int c = __builtin_ctz(t);
                 parent[c] = v;
                 vis |= 1u << c;
@@ -117,10 +118,17 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
             }
         }
         for (uint32_t v = 0; v < n; ++v) {
-            g.tree_desc[v] = 1u << v;
-            g.tree_parent_bit[v] = parent[v] >= 0 ? (1u << parent[v]) : 0u;
+            L.desc[v] = 1u << v;
+            L.pbit[v] = parent[v] >= 0 ? (1u << parent[v]) : 0u;
         }
-        for (int i = tail - 1; i > 0; --i) g.tree_desc[parent[order[i]]] |= g.tree_desc[order[i]];
+        for (int i = tail - 1; i > 0; --i) L.desc[parent[order[i]]] |= L.desc[order[i]];
+    }
+    // selectivities of the edges (u, v), u < v, grouped by v, u ascending
+    uint32_t at = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        L.selrow[v] = at;
+        for (uint32_t t = L.adj[v] & ((1u << v) - 1u); t; t &= t - 1)
+            L.sel[at++] = g.sel_full[__builtin_ctz(t) * 32 + v];
     }
     for (int b = 0; b < 4; ++b)
         for (uint32_t x = 0; x < 256; ++x) {
@@ -128,12 +136,17 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
             for (int j = 0; j < 8; ++j)
                 if ((x >> j) & 1u) {
                     const uint32_t v = 8u * b + j;
-                    if (v < n) u |= g.adj[v];
+                    if (v < n) u |= L.adj[v];
                 }
-            g.nbr_byte[b][x] = u;
+            L.nb[b][x] = u;
         }
     for (uint32_t a = 0; a <= 32; ++a)
-        for (uint32_t b = 0; b <= 32; ++b) g.binom[a * 33 + b] = (uint32_t)binom64(a, b);
+        for (uint32_t b = 0; b <= 32; ++b) L.binom[a * 33 + b] = (uint32_t)binom64(a, b);
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < 34; ++k) {
+        L.loff[k] = off;
+        if (k <= n) off += binom64(n, k);
+    }
     return MPDP_OK;
 }
 
@@ -143,8 +156,8 @@ double now_ms() {
 }
 
 mpdp_status leaf_only(const Query &q, mpdp_plan_node *plan, double *cost_out) {
-    plan[0] = mpdp_plan_node{-1, -1, 1u, MPDP_OP_SCAN, q.g.base_cost[0], q.g.card[0]};
-    *cost_out = q.g.base_cost[0];
+    plan[0] = mpdp_plan_node{-1, -1, 1u, MPDP_OP_SCAN, q.g.lds.bcost[0], q.g.lds.card[0]};
+    *cost_out = q.g.lds.bcost[0];
     return MPDP_OK;
 }
 
@@ -197,12 +210,12 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         const uint64_t nc = binom64(n, k);
         candidates += nc;
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 8], s));
-        HIPCHK(mpdp::launch_filter(dg, k, nc, list, cnt, s));
+        if (general) HIPCHK(mpdp::launch_filter(dg, k, nc, list, cnt, s));
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 7], s));
         if (general)
             HIPCHK(mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, cnt, memo, s));
-        else
-            HIPCHK(mpdp::launch_eval_tree(dg, q.cost_model, k, nc, list, cnt, memo, s));
+        else  // tree joins: unrank, filter and evaluate in one kernel per level
+            HIPCHK(mpdp::launch_level_tree(dg, q.cost_model, k, nc, cnt, memo, s));
         ++launches;
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 6], s));
     }

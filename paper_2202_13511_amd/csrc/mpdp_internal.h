@@ -13,21 +13,34 @@ namespace mpdp {
 
 constexpr int kMaxRel = 32;
 
-// Query information as the kernels read it.  Built on the host, uploaded
-// once per call (about 17 KB), staged into LDS by every workgroup.
-struct DevGraph {
-    uint32_t n, m, is_tree, cost_model;
-    uint32_t adj[kMaxRel];            // bit u of adj[v]: edge (u, v)
-    uint32_t tree_parent_bit[kMaxRel];// tree joins rooted at relation 0: bit of parent, 0 at the root
-    uint32_t tree_desc[kMaxRel];      // tree joins: relations of the subtree rooted at v
-    uint32_t nbr_byte[4][256];        // neighbours of a set, one table per byte of the bitmap
+// Per-workgroup copy of the query information, laid out on the host exactly
+// as the kernels keep it in LDS so that staging is a plain 16-byte copy.
+struct LdsImage {
+    uint64_t loff[34];                        // memo offset of level k: sum of C(n, j), j < k
     double card[kMaxRel];
-    double base_cost[kMaxRel];        // cost of scanning relation v under the chosen model
-    double sel[kMaxRel * kMaxRel];    // sel[u * 32 + v], symmetric, 0 without an edge
-    uint32_t binom[33 * 33];          // C(a, b) at [a * 33 + b]
+    double bcost[kMaxRel];                    // cost of scanning relation v under the model
+    double sel[kMaxRel * (kMaxRel - 1) / 2];  // per v: sel(u, v) of edges u < v, u ascending
+    uint32_t nb[4][256];                      // neighbours of a set, one table per bitmap byte
+    uint32_t adj[kMaxRel];                    // bit u of adj[v]: edge (u, v)
+    uint32_t pbit[kMaxRel];                   // tree joins rooted at 0: bit of the parent, 0 at the root
+    uint32_t desc[kMaxRel];                   // tree joins: relations of the subtree rooted at v
+    uint32_t selrow[kMaxRel];                 // first sel entry of relation v
+    uint32_t binom[33 * 33];                  // C(a, b) at [a * 33 + b]
+    uint32_t pad[3];
+};
+static_assert(sizeof(LdsImage) % 16 == 0, "LdsImage is copied in 16-byte units");
+
+// Query information as the kernels read it.  Built on the host, uploaded
+// once per call.
+struct DevGraph {
+    LdsImage lds;
+    uint32_t n, m, is_tree, cost_model;
+    double sel_full[kMaxRel * kMaxRel];  // sel[u * 32 + v], symmetric, 0 without an edge
 };
 
-// Dense memo, indexed by the relation-set bitmap.
+// Memo, level-compact: the entry of a relation set S sits at
+// level_off[|S|] + colex(S), colex(S) = sum over the i-th smallest member s_i
+// of S (i from 0) of C(s_i, i + 1).  One contiguous slab per level.
 struct MemoPtrs {
     double *cost;
     double *card;
@@ -47,8 +60,8 @@ struct Counters {
 hipError_t launch_init(const DevGraph *g, uint32_t n, MemoPtrs memo, Counters *cnt, hipStream_t s);
 hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t *list, Counters *cnt,
                          hipStream_t s);
-hipError_t launch_eval_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
-                            const uint32_t *list, const Counters *cnt, MemoPtrs memo, hipStream_t s);
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
+                             MemoPtrs memo, hipStream_t s);
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
                                const uint32_t *list, Counters *cnt, MemoPtrs memo, hipStream_t s);
 hipError_t launch_extract(const DevGraph *g, uint32_t n, MemoPtrs memo, mpdp_plan_node *plan,

@@ -1,13 +1,19 @@
 // gfx950 kernels of the MPDP level loop (Section 5, Alg. 5):
 //   k_init          memo init + base-relation fill
+//   k_level_tree    one level of Alg. 2 (tree join graphs): unrank, filter
+//                   and evaluate fused, one lane per connected set
 //   k_filter        unrank the k-subsets and keep the connected ones
-//   k_eval_tree     Alg. 2 (tree join graphs): one thread per connected set
 //   k_eval_general  Alg. 3 (block-based enumeration): one wave64 per set
 //   k_extract       rebuild the plan tree from the memo
 //
 // Everything is integer bitmap work plus a few IEEE binary64 operations per
 // join pair; nothing here is a dense contraction, so no MFMA.  Compiled with
 // -ffp-contract=off so every cost expression rounds exactly as written.
+//
+// Memo layout: level-compact.  The entry of S sits at
+// level_off[|S|] + colex(S), so one DP level is one contiguous slab and sets
+// evaluated together (consecutive colex ranks) gather from neighbouring
+// entries of the level below.
 #include <hip/hip_runtime.h>
 
 #include "mpdp_internal.h"
@@ -17,9 +23,14 @@ namespace {
 
 constexpr int kBlock = 256;         // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kFilterChunk = 8;     // consecutive ranks per lane in the filter
+constexpr int kFilterChunk = 16;    // consecutive ranks per lane in k_filter (<= 31)
+constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tree (1, 2 or 4)
+constexpr int kRing = 512;          // per-wave ring of connected sets (> 63 + 64 * kTreeChunkMax)
+constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
 constexpr int kEvalChunk = 16;      // block-local candidates per lane chunk
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
+
+static_assert(kRing >= 64 + 64 * kTreeChunkMax, "ring too small");
 
 // ---------------------------------------------------------------- bitmaps
 
@@ -63,27 +74,35 @@ __device__ __forceinline__ uint32_t deposit(uint32_t j, uint32_t mask) {
 
 // ---------------------------------------------------------------- LDS copy
 
-struct LdsGraph {
-    uint32_t nb[4][256];
-    uint32_t adj[kMaxRel];
-    uint32_t pbit[kMaxRel];
-    uint32_t desc[kMaxRel];
-    double card[kMaxRel];
-    double sel[kMaxRel * kMaxRel];
-};
+using LdsGraph = LdsImage;
 
-__device__ void stage_graph(const DevGraph *g, LdsGraph &L) {
-    const uint32_t *src = &g->nbr_byte[0][0];
-    uint32_t *dst = &L.nb[0][0];
-    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) dst[i] = src[i];
-    for (int i = threadIdx.x; i < kMaxRel * kMaxRel; i += blockDim.x) L.sel[i] = g->sel[i];
-    if (threadIdx.x < kMaxRel) {
-        L.adj[threadIdx.x] = g->adj[threadIdx.x];
-        L.pbit[threadIdx.x] = g->tree_parent_bit[threadIdx.x];
-        L.desc[threadIdx.x] = g->tree_desc[threadIdx.x];
-        L.card[threadIdx.x] = g->card[threadIdx.x];
-    }
+// Copy the host-built LDS image into the workgroup's LDS.
+__device__ __forceinline__ void stage_graph(const DevGraph *g, LdsGraph &L) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(&g->lds);
+    uint4 *dst = reinterpret_cast<uint4 *>(&L);
+    for (uint32_t i = threadIdx.x; i < sizeof(LdsGraph) / 16; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
+}
+
+// Memo index of T: level offset plus colex rank.
+__device__ __forceinline__ uint64_t memo_index(const LdsGraph &L, uint32_t T) {
+    uint32_t r = 0;
+    int i = 1;
+    for (uint32_t U = T; U; U &= U - 1, ++i) r += L.binom[ctz32(U) * 33 + i];
+    return L.loff[i - 1] + r;
+}
+
+// Colex unrank of rank r among the k-subsets of n relations.
+__device__ __forceinline__ uint32_t colex_unrank(const uint32_t *binom, int n, int k, uint32_t r) {
+    uint32_t S = 0;
+    int c = n - 1;
+    for (int i = k; i >= 1; --i) {
+        while (binom[c * 33 + i] > r) --c;
+        r -= binom[c * 33 + i];
+        S |= 1u << c;
+        --c;
+    }
+    return S;
 }
 
 // ---------------------------------------------------------------- cost
@@ -95,8 +114,9 @@ __device__ __forceinline__ double card_of(const LdsGraph &L, uint32_t S) {
     for (uint32_t T = S; T; T &= T - 1) {
         const int v = ctz32(T);
         c = c * L.card[v];
-        for (uint32_t U = L.adj[v] & S & ((1u << v) - 1u); U; U &= U - 1)
-            c = c * L.sel[ctz32(U) * kMaxRel + v];
+        const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+        for (uint32_t U = lower & S; U; U &= U - 1)
+            c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
     }
     return c < 1.0 ? 1.0 : c;
 }
@@ -122,17 +142,18 @@ __device__ __forceinline__ void offer(Key &best, double cost, uint32_t left, uin
     if (key_less(k, best)) best = k;
 }
 
-// Cost both orientations of the csg-cmp pair (A, B) of S and keep the best.
+// Cost both orientations of the csg-cmp pair (A, B) of S, whose memo entries
+// sit at ia and ib, and keep the best.
 template <int CM>
-__device__ __forceinline__ void eval_pair(const MemoPtrs &M, uint32_t A, uint32_t B, double cardS,
-                                          Key &best) {
-    const double cA = M.cost[A], cB = M.cost[B];
+__device__ __forceinline__ void eval_pair(const MemoPtrs &M, uint32_t A, uint32_t B, uint64_t ia, uint64_t ib,
+                                          double cardS, Key &best) {
+    const double cA = M.cost[ia], cB = M.cost[ib];
     const double base = cA + cB;
     if (CM == MPDP_COST_COUT) {
         // symmetric: both orientations cost the same, the smaller left wins
         offer(best, base + cardS, A < B ? A : B, MPDP_OP_JOIN);
     } else {
-        const double kA = M.card[A], kB = M.card[B];
+        const double kA = M.card[ia], kB = M.card[ib];
         const double out = 0.01 * cardS;
         const double hjA = ((base + 0.0125 * kB) + 0.0025 * kA) + out;  // A outer, B hashed
         const double nlA = (base + (0.0025 * kA) * kB) + out;
@@ -143,99 +164,234 @@ __device__ __forceinline__ void eval_pair(const MemoPtrs &M, uint32_t A, uint32_
     }
 }
 
-__device__ __forceinline__ void store_best(const MemoPtrs &M, uint32_t S, const Key &b, double cardS) {
-    M.cost[S] = __longlong_as_double((long long)b.c);
-    M.card[S] = cardS;
-    M.left[S] = b.l;
-    M.op[S] = (uint8_t)b.op;
+__device__ __forceinline__ void store_best(const MemoPtrs &M, uint64_t at, const Key &b, double cardS) {
+    M.cost[at] = __longlong_as_double((long long)b.c);
+    M.card[at] = cardS;
+    M.left[at] = b.l;
+    M.op[at] = (uint8_t)b.op;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------- kernels
 
 __global__ void k_init(const DevGraph *g, uint32_t n, MemoPtrs M, Counters *cnt) {
     const uint32_t t = threadIdx.x;
-    if (t < n) {
-        const uint32_t s = 1u << t;
-        M.cost[s] = g->base_cost[t];
-        M.card[s] = g->card[t];
-        M.left[s] = 0;
-        M.op[s] = MPDP_OP_SCAN;
+    if (t < n) {  // colex({t}) = t, level 1 starts at 1
+        const uint64_t at = g->lds.loff[1] + t;
+        M.cost[at] = g->lds.bcost[t];
+        M.card[at] = g->lds.card[t];
+        M.left[at] = 0;
+        M.op[at] = MPDP_OP_SCAN;
     }
     uint32_t *words = reinterpret_cast<uint32_t *>(cnt);
     for (uint32_t i = t; i < sizeof(Counters) / 4; i += blockDim.x) words[i] = 0;
 }
 
-// Unrank + filter (Alg. 5 unrank and filter steps, fused).  Each lane takes
-// kFilterChunk consecutive colex ranks: it unranks the first with the
-// combinatorial number system and steps to the next k-subsets with the
-// same-popcount successor.  Connected sets are compacted with a wave ballot
-// and one atomic per wave and step.
+// Cost both orientations of the pair (A, B) of S from the two sides' memo
+// values and keep the best.
+template <int CM>
+__device__ __forceinline__ void eval_vals(uint32_t A, uint32_t B, double cA, double cB, double kA, double kB,
+                                          double cardS, Key &best) {
+    const double base = cA + cB;
+    if (CM == MPDP_COST_COUT) {
+        offer(best, base + cardS, A < B ? A : B, MPDP_OP_JOIN);
+    } else {
+        const double out = 0.01 * cardS;
+        const double hjA = ((base + 0.0125 * kB) + 0.0025 * kA) + out;  // A outer, B hashed
+        const double nlA = (base + (0.0025 * kA) * kB) + out;
+        const double hjB = ((base + 0.0125 * kA) + 0.0025 * kB) + out;  // B outer, A hashed
+        const double nlB = (base + (0.0025 * kB) * kA) + out;
+        if (hjA <= nlA) offer(best, hjA, A, MPDP_OP_HASH); else offer(best, nlA, A, MPDP_OP_NESTLOOP);
+        if (hjB <= nlB) offer(best, hjB, B, MPDP_OP_HASH); else offer(best, nlB, B, MPDP_OP_NESTLOOP);
+    }
+}
+
+// Alg. 2 for one connected S of a tree join graph.  With the tree rooted at
+// relation 0, removing the edge (parent(c), c) of G[S] gives the pair
+// (desc(c) & S, S minus that) for every c in S whose parent is in S.
+// When desc(c) & S = {c} the complement's colex rank follows from prefix
+// sums: rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and
+// the singleton's cost and card come from LDS.  Pairs are taken in batches
+// of kPairBatch whose memo gathers are all issued before any is used.
+template <int CM>
+__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint64_t off_k,
+                                              uint64_t off_km1) {
+    constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 8 : 4;
+    uint32_t rank = 0, bsum = 0;
+    {
+        int i = 0;
+        for (uint32_t T = S; T; T &= T - 1, ++i) {
+            const int v = ctz32(T);
+            rank += L.binom[v * 33 + i + 1];
+            bsum += L.binom[v * 33 + i];
+        }
+    }
+    const double cardS = card_of(L, S);
+    Key best = worst_key();
+    uint32_t pa = 0, pb = 0, T = S;
+    int i = 0;
+    while (T) {
+        uint32_t Av[kPairBatch];
+        uint64_t ia[kPairBatch], ib[kPairBatch];
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            Av[u] = 0;
+            ia[u] = 0;
+            ib[u] = 0;
+            while (T) {
+                const int c = ctz32(T);
+                T &= T - 1;
+                const uint32_t a_i = L.binom[c * 33 + i + 1];
+                pb += L.binom[c * 33 + i];
+                ++i;
+                const bool take = (S & L.pbit[c]) != 0;
+                if (take) {
+                    const uint32_t A = L.desc[c] & S;
+                    Av[u] = A;
+                    if (A == (1u << c)) {
+                        ia[u] = ~0ull;  // singleton: cost and card from LDS
+                        ib[u] = off_km1 + (pa + (bsum - pb));
+                    } else {
+                        ia[u] = memo_index(L, A);
+                        ib[u] = memo_index(L, S ^ A);
+                    }
+                }
+                pa += a_i;
+                if (take) break;
+            }
+        }
+        double cA[kPairBatch], cB[kPairBatch], kA[kPairBatch], kB[kPairBatch];
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            if (!Av[u]) continue;
+            cB[u] = M.cost[ib[u]];
+            if (CM != MPDP_COST_COUT) kB[u] = M.card[ib[u]];
+            if (ia[u] == ~0ull) {
+                const int c = ctz32(Av[u]);
+                cA[u] = L.bcost[c];
+                kA[u] = L.card[c];
+            } else {
+                cA[u] = M.cost[ia[u]];
+                if (CM != MPDP_COST_COUT) kA[u] = M.card[ia[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u)
+            if (Av[u]) eval_vals<CM>(Av[u], S ^ Av[u], cA[u], cB[u], kA[u], kB[u], cardS, best);
+    }
+    store_best(M, off_k + rank, best, cardS);
+}
+
+// One DP level of a tree join graph, Alg. 5's unrank, filter, evaluate,
+// prune and scatter fused.  Each wave walks ranges of 64 * kTreeChunk colex
+// ranks (kTreeChunk consecutive ranks per lane: unrank the first, then the
+// same-popcount successor), appends the connected sets to its LDS ring in
+// rank order, and evaluates 64 of them at a time, one per lane, so no lane
+// idles on a disconnected candidate.
+template <int CM, int kTreeChunk>
+__global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32_t k, uint64_t ncand,
+                                                       Counters *cnt, MemoPtrs M) {
+    __shared__ __align__(16) LdsGraph L;
+    __shared__ uint32_t ring_all[kWaves][kRing];
+    stage_graph(g, L);
+    const int n = (int)g->n;
+    const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below_me = (1ull << lane) - 1ull;
+    uint32_t *ring = ring_all[threadIdx.x >> 6];
+    const uint64_t per_wave = 64ull * kTreeChunk;
+    const uint64_t waves = (uint64_t)gridDim.x * kWaves;
+    const uint64_t off_k = L.loff[k], off_km1 = L.loff[k - 1];
+    uint32_t head = 0, tail = 0;  // ring cursors, uniform across the wave
+
+    for (uint64_t w = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); w * per_wave < ncand; w += waves) {
+        const uint64_t r0 = w * per_wave + (uint64_t)lane * kTreeChunk;
+        uint32_t S = r0 < ncand ? colex_unrank(L.binom, n, (int)k, (uint32_t)r0) : 0u;
+        uint32_t sets[kTreeChunk];
+        uint32_t keep = 0;
+#pragma unroll
+        for (int j = 0; j < kTreeChunk; ++j) {
+            sets[j] = S;
+            if (r0 + (uint64_t)j < ncand) {
+                if (grow(L.nb, lowbit(S), S) == S) keep |= 1u << j;
+                S = next_subset(S);
+            }
+        }
+        const uint32_t mine = (uint32_t)popc32(keep);
+        uint32_t before = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)  // exclusive prefix of `mine` (<= 4) across the wave
+            before += (uint32_t)__popcll(__ballot((mine >> b) & 1u) & below_me) << b;
+        const uint32_t total = (uint32_t)__shfl((int)(before + mine), 63);
+        uint32_t pos = tail + before;
+#pragma unroll
+        for (int j = 0; j < kTreeChunk; ++j)
+            if (keep & (1u << j)) ring[(pos++) & (kRing - 1)] = sets[j];
+        tail += total;
+        wave_sync_lds();
+        while (tail - head >= 64) {
+            const uint32_t s = ring[(head + lane) & (kRing - 1)];
+            eval_tree_set<CM>(L, M, s, off_k, off_km1);
+            head += 64;
+        }
+        wave_sync_lds();
+    }
+    if (tail != head && lane < tail - head) {
+        const uint32_t s = ring[(head + lane) & (kRing - 1)];
+        eval_tree_set<CM>(L, M, s, off_k, off_km1);
+    }
+    if (lane == 0 && tail) atomicAdd(&cnt->level_count[k], tail);
+}
+
+// Unrank + filter for the block kernel.  Each lane takes kFilterChunk
+// consecutive colex ranks; the wave compacts its connected sets in rank
+// order (each lane's count is prefixed across the wave with one ballot per
+// count bit) and one atomic per wave reserves the output range.
 __global__ __launch_bounds__(kBlock) void k_filter(const DevGraph *g, uint32_t k, uint64_t ncand,
                                                    uint32_t *list, Counters *cnt) {
-    __shared__ uint32_t nb[4][256];
-    __shared__ uint32_t binom[33 * 33];
-    for (int i = threadIdx.x; i < 1024; i += blockDim.x) (&nb[0][0])[i] = (&g->nbr_byte[0][0])[i];
-    for (int i = threadIdx.x; i < 33 * 33; i += blockDim.x) binom[i] = g->binom[i];
-    __syncthreads();
+    __shared__ __align__(16) LdsGraph L;
+    stage_graph(g, L);
+    const uint32_t (*nb)[256] = L.nb;
+    const uint32_t *binom = L.binom;
 
     const int n = (int)g->n;
     const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below_me = (1ull << lane) - 1ull;
     const uint64_t per_wave = 64ull * kFilterChunk;
     const uint64_t waves = (uint64_t)gridDim.x * kWaves;
     uint32_t *level_count = &cnt->level_count[k];
 
     for (uint64_t w = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); w * per_wave < ncand; w += waves) {
         const uint64_t r0 = w * per_wave + (uint64_t)lane * kFilterChunk;
-        uint32_t S = 0;
-        if (r0 < ncand) {  // colex unrank of r0
-            uint32_t r = (uint32_t)r0;
-            int c = n - 1;
-            for (int i = (int)k; i >= 1; --i) {
-                while (binom[c * 33 + i] > r) --c;
-                r -= binom[c * 33 + i];
-                S |= 1u << c;
-                --c;
-            }
-        }
+        uint32_t S = r0 < ncand ? colex_unrank(binom, n, (int)k, (uint32_t)r0) : 0u;
+        uint32_t sets[kFilterChunk];
+        uint32_t keep = 0;
+#pragma unroll
         for (int j = 0; j < kFilterChunk; ++j) {
-            const bool valid = r0 + (uint64_t)j < ncand;
-            bool keep = false;
-            if (valid) keep = grow(nb, lowbit(S), S) == S;
-            const unsigned long long mask = __ballot(keep);
-            if (mask) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(level_count, (uint32_t)__popcll(mask));
-                base = __shfl(base, 0);
-                if (keep) {
-                    const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-                    list[base + below] = S;
-                }
+            sets[j] = S;
+            if (r0 + (uint64_t)j < ncand) {
+                if (grow(nb, lowbit(S), S) == S) keep |= 1u << j;
+                S = next_subset(S);
             }
-            if (valid) S = next_subset(S);
         }
-    }
-}
-
-// Alg. 2 on a tree join graph.  With the tree rooted at relation 0, the pair
-// obtained by removing the edge (parent(c), c) of G[S] is
-// (desc(c) & S, S minus that), for every c in S whose parent is in S.
-template <int CM>
-__global__ __launch_bounds__(kBlock) void k_eval_tree(const DevGraph *g, uint32_t k, const uint32_t *list,
-                                                      const Counters *cnt, MemoPtrs M) {
-    __shared__ LdsGraph L;
-    stage_graph(g, L);
-    const uint32_t count = cnt->level_count[k];
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
-        const uint32_t S = list[i];
-        const double cardS = card_of(L, S);
-        Key best = worst_key();
-        for (uint32_t T = S; T; T &= T - 1) {
-            const int c = ctz32(T);
-            if (!(S & L.pbit[c])) continue;  // c is the root of G[S]
-            const uint32_t A = L.desc[c] & S;
-            eval_pair<CM>(M, A, S ^ A, cardS, best);
-        }
-        store_best(M, S, best, cardS);
+        const uint32_t mine = (uint32_t)popc32(keep);
+        uint32_t before = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b)  // exclusive prefix of `mine` (<= 16) across the wave
+            before += (uint32_t)__popcll(__ballot((mine >> b) & 1u) & below_me) << b;
+        uint32_t total = before + mine;
+        total = (uint32_t)__shfl((int)total, 63);
+        if (total == 0) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(level_count, total);
+        base = (uint32_t)__shfl((int)base, 0) + before;
+#pragma unroll
+        for (int j = 0; j < kFilterChunk; ++j)
+            if (keep & (1u << j)) list[base++] = sets[j];
     }
 }
 
@@ -263,9 +419,8 @@ struct WaveScratch {
 
 // Alg. 3: one wave64 per connected set S.
 //  1. cut vertices of G[S]: lane v checks whether G[S - v] is connected;
-//  2. blocks: split S at a cut vertex into pieces {x} + component, recurse
-//     until a piece has no cut vertex of its own (piece-local cut vertices
-//     are the cut vertices of S inside the piece, minus its attachment);
+//  2. blocks: split S at a cut vertex into pieces {x} + component, and
+//     split pieces again until a piece has no cut vertex of its own;
 //  3. lanes share the block-local candidates lb (lb holds the block's lowest
 //     relation, lb != block, so each unordered pair is visited once and both
 //     orientations are costed); a candidate is a pair when G[lb] and G[rb]
@@ -274,7 +429,7 @@ struct WaveScratch {
 template <int CM>
 __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint32_t k, const uint32_t *list,
                                                          Counters *cnt, MemoPtrs M) {
-    __shared__ LdsGraph L;
+    __shared__ __align__(16) LdsGraph L;
     __shared__ WaveScratch WS[kWaves];
     stage_graph(g, L);
     const int lane = threadIdx.x & 63;
@@ -293,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
         }
         const uint32_t A = (uint32_t)__ballot(cut);
 
-        // 2. blocks (uniform control flow; the stack lives one entry per lane)
+        // 2. blocks (uniform control flow; the stack lives one entry per lane).
         // A piece is a union of blocks of S; its attachment set holds the
         // split vertices it still contains, which are not cut vertices of
         // the piece.  Every other cut vertex of S inside the piece is.
@@ -323,13 +478,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
         }
 
         // 3. per-block candidate counts (lane i owns block i)
-        uint32_t half = 0, chunks = 0, complete = 0;
-        unsigned long long evalb = 0;
+        uint32_t chunks = 0, complete = 0;
         if (lane < nblk) {
             const int bs = popc32(myblk);
-            half = (1u << (bs - 1)) - 1u;
+            const uint32_t half = (1u << (bs - 1)) - 1u;
             chunks = (half + kEvalChunk - 1) / kEvalChunk;
-            evalb = (1ull << bs) - 2ull;
             uint32_t deg = 0;
             for (uint32_t T = myblk; T; T &= T - 1) deg += popc32(L.adj[ctz32(T)] & myblk);
             complete = deg == (uint32_t)(bs * (bs - 1));
@@ -341,13 +494,10 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
             acc += c;
             my_eval += (lane == 0) ? (1ull << popc32(rdlane(myblk, i))) - 2ull : 0ull;
         }
-        (void)evalb;
         const uint32_t total_chunks = acc;
         if (lane < nblk) { W.blk[lane] = myblk; W.full[lane] = complete; W.cpre[lane] = mypre; }
         if (lane == 0) W.cpre[nblk] = total_chunks;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_lds();
 
         const double cardS = card_of(L, S);
         Key best = worst_key();
@@ -370,12 +520,13 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
                 }
                 ++my_ccp;
                 const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
-                eval_pair<CM>(M, Sl, S ^ Sl, cardS, best);
+                const uint32_t Sr = S ^ Sl;
+                eval_pair<CM>(M, Sl, Sr, memo_index(L, Sl), memo_index(L, Sr), cardS, best);
             }
         }
         best = wave_min(best);
-        if (lane == 0) store_best(M, S, best, cardS);
-        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) store_best(M, memo_index(L, S), best, cardS);
+        wave_sync_lds();
     }
 
     // one atomic per wave for the counters
@@ -389,39 +540,55 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
     }
 }
 
+__device__ uint64_t memo_index_g(const DevGraph *g, uint32_t T) {
+    uint32_t r = 0;
+    int i = 1;
+    for (uint32_t U = T; U; U &= U - 1, ++i) r += g->lds.binom[ctz32(U) * 33 + i];
+    return g->lds.loff[i - 1] + r;
+}
+
 // Rebuild the plan (Section 5: fetched recursively through left/right) in
 // post-order on one thread; n - 1 memo reads.
 __global__ void k_extract(const DevGraph *g, uint32_t n, MemoPtrs M, mpdp_plan_node *plan, double *root_cost,
                           Counters *cnt) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     for (uint32_t v = 0; v < n; ++v) {
-        const uint32_t s = 1u << v;
-        plan[v] = mpdp_plan_node{-1, -1, s, MPDP_OP_SCAN, M.cost[s], M.card[s]};
+        const uint64_t at = g->lds.loff[1] + v;
+        plan[v] = mpdp_plan_node{-1, -1, 1u << v, MPDP_OP_SCAN, M.cost[at], M.card[at]};
     }
     const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
-    *root_cost = M.cost[full];
+    *root_cost = M.cost[memo_index_g(g, full)];
     if (n == 1) return;
-    struct Frame { uint32_t S; int stage; int li; };
+    struct Frame { uint32_t S; uint32_t L; int stage; int li; };
     Frame st[33];
     int sp = 0, next = (int)n, ret = -1, guard = 0;
-    st[sp++] = Frame{full, 0, -1};
+    st[sp++] = Frame{full, M.left[memo_index_g(g, full)], 0, -1};
     while (sp > 0 && ++guard < 4 * 64) {
         Frame &f = st[sp - 1];
-        const uint32_t Lft = M.left[f.S];
+        const uint32_t Lft = f.L;
         if (Lft == 0 || (Lft & ~f.S) != 0 || Lft == f.S) { cnt->extract_error = 1; return; }
         const uint32_t Rgt = f.S & ~Lft;
         if (f.stage == 0) {
             f.stage = 1;
             if ((Lft & (Lft - 1)) == 0) ret = ctz32(Lft);
-            else { if (sp >= 33) { cnt->extract_error = 2; return; } st[sp++] = Frame{Lft, 0, -1}; continue; }
+            else {
+                if (sp >= 33) { cnt->extract_error = 2; return; }
+                st[sp++] = Frame{Lft, M.left[memo_index_g(g, Lft)], 0, -1};
+                continue;
+            }
         }
         if (f.stage == 1) {
             f.li = ret;
             f.stage = 2;
             if ((Rgt & (Rgt - 1)) == 0) ret = ctz32(Rgt);
-            else { if (sp >= 33) { cnt->extract_error = 2; return; } st[sp++] = Frame{Rgt, 0, -1}; continue; }
+            else {
+                if (sp >= 33) { cnt->extract_error = 2; return; }
+                st[sp++] = Frame{Rgt, M.left[memo_index_g(g, Rgt)], 0, -1};
+                continue;
+            }
         }
-        plan[next] = mpdp_plan_node{f.li, ret, f.S, (uint32_t)M.op[f.S], M.cost[f.S], M.card[f.S]};
+        const uint64_t at = memo_index_g(g, f.S);
+        plan[next] = mpdp_plan_node{f.li, ret, f.S, (uint32_t)M.op[at], M.cost[at], M.card[at]};
         ret = next++;
         --sp;
     }
@@ -448,13 +615,27 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_eval_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
-                            const uint32_t *list, const Counters *cnt, MemoPtrs memo, hipStream_t s) {
-    const uint32_t grid = grid_for(ncand, kBlock);
-    if (cost_model == MPDP_COST_COUT)
-        hipLaunchKernelGGL(k_eval_tree<MPDP_COST_COUT>, dim3(grid), dim3(kBlock), 0, s, g, k, list, cnt, memo);
-    else
-        hipLaunchKernelGGL(k_eval_tree<MPDP_COST_PGLIKE>, dim3(grid), dim3(kBlock), 0, s, g, k, list, cnt, memo);
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
+                             MemoPtrs memo, hipStream_t s) {
+    // Fewer consecutive ranks per lane on small levels, so that even they
+    // spread over some thousands of waves; a persistent-sized grid on large
+    // ones, so each workgroup stages the query information once.
+    constexpr uint64_t kWantWaves = 8192;
+    const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
+    uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
+    const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > kPersistGrid ? kPersistGrid : blocks));
+#define MPDP_LEVEL_TREE(CMV, CH) \
+    hipLaunchKernelGGL((k_level_tree<CMV, CH>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo)
+    if (cost_model == MPDP_COST_COUT) {
+        if (chunk == 4) MPDP_LEVEL_TREE(MPDP_COST_COUT, 4);
+        else if (chunk == 2) MPDP_LEVEL_TREE(MPDP_COST_COUT, 2);
+        else MPDP_LEVEL_TREE(MPDP_COST_COUT, 1);
+    } else {
+        if (chunk == 4) MPDP_LEVEL_TREE(MPDP_COST_PGLIKE, 4);
+        else if (chunk == 2) MPDP_LEVEL_TREE(MPDP_COST_PGLIKE, 2);
+        else MPDP_LEVEL_TREE(MPDP_COST_PGLIKE, 1);
+    }
+#undef MPDP_LEVEL_TREE
     return hipGetLastError();
 }
 

@@ -169,14 +169,33 @@ def mpdp_optimize_ws(query, cost_model: int, ws, stream=None, flags: int = 0) ->
     return _result(n, plan, cost, stats)
 
 
+def memo_index(n: int) -> np.ndarray:
+    """Memo index of every relation-set bitmap S < 2^n under the level-compact
+    layout documented at mpdp_memo_layout: off(|S|) + colex(S)."""
+    from math import comb
+    S = np.arange(1 << n, dtype=np.uint64)
+    pop = np.zeros(1 << n, dtype=np.int64)
+    rank = np.zeros(1 << n, dtype=np.uint64)
+    for v in range(n):
+        has = ((S >> np.uint64(v)) & np.uint64(1)).astype(bool)
+        table = np.array([comb(v, p + 1) for p in range(n + 1)], dtype=np.uint64)
+        rank[has] += table[pop[has]]
+        pop += has
+    off = np.zeros(n + 2, dtype=np.uint64)
+    for k in range(1, n + 2):
+        off[k] = off[k - 1] + np.uint64(comb(n, k - 1))
+    return off[pop] + rank
+
+
 def memo_arrays(ws, n: int) -> dict:
-    """Host copies of the memo arrays left in a workspace by mpdp_optimize_ws."""
+    """Host copies of the memo arrays left in a workspace by mpdp_optimize_ws,
+    re-indexed by relation-set bitmap (entry S at position S)."""
     lay = mpdp_memo_layout(n)
     N = 1 << n
-    raw = ws
+    idx = memo_index(n)
     out = {}
     for name, dt, width in (("cost", np.float64, 8), ("card", np.float64, 8), ("left", np.uint32, 4),
                             ("op", np.uint8, 1)):
-        seg = raw[lay[name]: lay[name] + N * width].cpu().numpy()
-        out[name] = seg.view(dt)
+        seg = ws[lay[name]: lay[name] + N * width].cpu().numpy().view(dt)
+        out[name] = seg[idx]
     return out
