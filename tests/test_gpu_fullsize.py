@@ -1,0 +1,92 @@
+"""GPU parity at the full workload sizes against stored oracle results.
+
+tests/golden/oracle_fullsize.json is written by
+tests/golden/make_oracle_golden.py from the CPU oracle alone.  Every query
+is optimized through the C-ABI in the launch configuration the benchmark
+uses; the root cost (bit pattern), every join node of the plan, the counters
+and 32 sampled memo entries must match exactly.
+"""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+from paper_2202_13511_amd import mpdp, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD_PATH = os.path.join(os.path.dirname(__file__), "golden", "oracle_fullsize.json")
+GOLD = json.load(open(GOLD_PATH))["queries"] if os.path.exists(GOLD_PATH) else []
+
+
+def make_query(g):
+    if g["kind"] == "star":
+        return W.star(g["n"], g["seed"])
+    if g["kind"] == "snowflake":
+        return W.snowflake(g["n"], g["seed"])
+    if g["kind"] == "clique":
+        return W.clique(g["n"], g["seed"])
+    if g["kind"] == "cycle_chords":
+        return W.cycle_chords(g["seed"])
+    raise ValueError(g["kind"])
+
+
+def memo_position(n, S):
+    """off(|S|) + colex(S) (layout documented at mpdp_memo_layout)."""
+    pos, r = 0, 0
+    for v in range(n):
+        if S >> v & 1:
+            r += comb(v, pos + 1)
+            pos += 1
+    return sum(comb(n, j) for j in range(pos)) + r
+
+
+def sampled_entries(ws, n, sets):
+    import torch
+    lay = mpdp.mpdp_memo_layout(n)
+    N = 1 << n
+    idx = torch.tensor([memo_position(n, S) for S in sets], dtype=torch.int64, device=ws.device)
+    cost = ws[lay["cost"]: lay["cost"] + 8 * N].view(torch.int64)[idx].cpu().numpy().view(np.uint64)
+    card = ws[lay["card"]: lay["card"] + 8 * N].view(torch.int64)[idx].cpu().numpy().view(np.uint64)
+    left = ws[lay["left"]: lay["left"] + 4 * N].view(torch.int32)[idx].cpu().numpy().view(np.uint32)
+    op = ws[lay["op"]: lay["op"] + N][idx].cpu().numpy()
+    return cost, card, left, op
+
+
+KINDS = [("star", 12), ("star", 25), ("snowflake", 25), ("clique", 18), ("cycle_chords", None)]
+
+
+@pytest.mark.parametrize("kind,n", KINDS, ids=[f"{k}{n or ''}" for k, n in KINDS])
+def test_fullsize_parity(kind, n):
+    import torch
+    qs = [g for g in GOLD if g["kind"] == kind and (n is None or g["n"] == n)]
+    if not qs:
+        pytest.skip("no stored oracle results for this workload")
+    wss = {}
+    for g in qs:
+        q = make_query(g)
+        assert q.n == g["n"] and q.m == g["m"], g["name"]
+        key = (q.n, g["cost_model"])
+        if key not in wss:
+            wss.clear()
+            torch.cuda.empty_cache()
+            wss[key] = mpdp.workspace(q.n, g["cost_model"], "cuda")
+        ws = wss[key]
+        print(f"{g['name']} cm={g['cost_model']}", flush=True)
+        res = mpdp.mpdp_optimize_ws(q, g["cost_model"], ws)
+        assert f"{int(np.float64(res.cost).view(np.uint64)):016x}" == g["root_cost"], g["name"]
+        joins = [[nd["relset"], res.plan[nd["left"]]["relset"], nd["op"]] for nd in res.plan[q.n:]]
+        assert joins == g["joins"], g["name"]
+        st = res.stats
+        assert st["connected_sets"] == g["connected_sets"], g["name"]
+        assert st["ccp_pairs"] == g["ccp_pairs"], g["name"]
+        assert st["evaluated_pairs"] == g["evaluated_pairs"], g["name"]
+        sets = [s[0] for s in g["samples"]]
+        cost, card, left, op = sampled_entries(ws, q.n, sets)
+        for i, (S, c, k, L, o) in enumerate(g["samples"]):
+            assert f"{int(cost[i]):016x}" == c and f"{int(card[i]):016x}" == k, (g["name"], S)
+            assert int(left[i]) == L and int(op[i]) == o, (g["name"], S)
+    wss.clear()
+    torch.cuda.empty_cache()
