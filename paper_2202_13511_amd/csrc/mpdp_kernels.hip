@@ -25,12 +25,12 @@ constexpr int kBlock = 256;         // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kFilterChunk = 16;    // consecutive ranks per lane in k_filter (<= 31)
 constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tree (1, 2 or 4)
-constexpr int kRing = 512;          // per-wave ring of connected sets (> 63 + 64 * kTreeChunkMax)
+constexpr int kRing = 384;          // per-wave ring of connected sets (>= 63 + 64 * kTreeChunkMax)
 constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
 constexpr int kEvalChunk = 16;      // block-local candidates per lane chunk
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
 
-static_assert(kRing >= 64 + 64 * kTreeChunkMax, "ring too small");
+static_assert(kRing >= 63 + 64 * kTreeChunkMax, "ring too small");
 
 // ---------------------------------------------------------------- bitmaps
 
@@ -215,12 +215,14 @@ __device__ __forceinline__ void eval_vals(uint32_t A, uint32_t B, double cA, dou
 // relation 0, removing the edge (parent(c), c) of G[S] gives the pair
 // (desc(c) & S, S minus that) for every c in S whose parent is in S.
 // When desc(c) & S = {c} the complement's colex rank follows from prefix
-// sums: rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and
-// the singleton's cost and card come from LDS.  Pairs are taken in batches
-// of kPairBatch whose memo gathers are all issued before any is used.
+// sums, rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and the
+// singleton's cost and card come from LDS.  Pairs are taken in batches of
+// kPairBatch whose memo gathers are all issued before any is used; the batch
+// keeps 32-bit ranks only, so that eight waves fit on a SIMD.
 template <int CM>
 __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint64_t off_k,
-                                              uint64_t off_km1) {
+                                              const double *__restrict__ cost_km1,
+                                              const double *__restrict__ card_km1) {
     constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 8 : 4;
     uint32_t rank = 0, bsum = 0;
     {
@@ -236,13 +238,11 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
     uint32_t pa = 0, pb = 0, T = S;
     int i = 0;
     while (T) {
-        uint32_t Av[kPairBatch];
-        uint64_t ia[kPairBatch], ib[kPairBatch];
+        uint32_t Av[kPairBatch], rk[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
             Av[u] = 0;
-            ia[u] = 0;
-            ib[u] = 0;
+            rk[u] = 0;
             while (T) {
                 const int c = ctz32(T);
                 T &= T - 1;
@@ -251,15 +251,8 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
                 ++i;
                 const bool take = (S & L.pbit[c]) != 0;
                 if (take) {
-                    const uint32_t A = L.desc[c] & S;
-                    Av[u] = A;
-                    if (A == (1u << c)) {
-                        ia[u] = ~0ull;  // singleton: cost and card from LDS
-                        ib[u] = off_km1 + (pa + (bsum - pb));
-                    } else {
-                        ia[u] = memo_index(L, A);
-                        ib[u] = memo_index(L, S ^ A);
-                    }
+                    Av[u] = L.desc[c] & S;
+                    rk[u] = pa + (bsum - pb);  // colex rank of S - {c}
                 }
                 pa += a_i;
                 if (take) break;
@@ -268,16 +261,22 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
         double cA[kPairBatch], cB[kPairBatch], kA[kPairBatch], kB[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
-            if (!Av[u]) continue;
-            cB[u] = M.cost[ib[u]];
-            if (CM != MPDP_COST_COUT) kB[u] = M.card[ib[u]];
-            if (ia[u] == ~0ull) {
-                const int c = ctz32(Av[u]);
+            const uint32_t A = Av[u];
+            if (!A) continue;
+            if ((A & (A - 1)) == 0) {
+                cB[u] = cost_km1[rk[u]];
+                if (CM != MPDP_COST_COUT) kB[u] = card_km1[rk[u]];
+                const int c = ctz32(A);
                 cA[u] = L.bcost[c];
                 kA[u] = L.card[c];
             } else {
-                cA[u] = M.cost[ia[u]];
-                if (CM != MPDP_COST_COUT) kA[u] = M.card[ia[u]];
+                const uint64_t ia = memo_index(L, A), ib = memo_index(L, S ^ A);
+                cA[u] = M.cost[ia];
+                cB[u] = M.cost[ib];
+                if (CM != MPDP_COST_COUT) {
+                    kA[u] = M.card[ia];
+                    kB[u] = M.card[ib];
+                }
             }
         }
 #pragma unroll
@@ -306,6 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     const uint64_t per_wave = 64ull * kTreeChunk;
     const uint64_t waves = (uint64_t)gridDim.x * kWaves;
     const uint64_t off_k = L.loff[k], off_km1 = L.loff[k - 1];
+    const double *cost_km1 = M.cost + off_km1;
+    const double *card_km1 = M.card + off_km1;
     uint32_t head = 0, tail = 0;  // ring cursors, uniform across the wave
 
     for (uint64_t w = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); w * per_wave < ncand; w += waves) {
@@ -330,19 +331,19 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
         uint32_t pos = tail + before;
 #pragma unroll
         for (int j = 0; j < kTreeChunk; ++j)
-            if (keep & (1u << j)) ring[(pos++) & (kRing - 1)] = sets[j];
+            if (keep & (1u << j)) ring[(pos++) % kRing] = sets[j];
         tail += total;
         wave_sync_lds();
         while (tail - head >= 64) {
-            const uint32_t s = ring[(head + lane) & (kRing - 1)];
-            eval_tree_set<CM>(L, M, s, off_k, off_km1);
+            const uint32_t s = ring[(head + lane) % kRing];
+            eval_tree_set<CM>(L, M, s, off_k, cost_km1, card_km1);
             head += 64;
         }
         wave_sync_lds();
     }
     if (tail != head && lane < tail - head) {
-        const uint32_t s = ring[(head + lane) & (kRing - 1)];
-        eval_tree_set<CM>(L, M, s, off_k, off_km1);
+        const uint32_t s = ring[(head + lane) % kRing];
+        eval_tree_set<CM>(L, M, s, off_k, cost_km1, card_km1);
     }
     if (lane == 0 && tail) atomicAdd(&cnt->level_count[k], tail);
 }
@@ -540,59 +541,82 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
     }
 }
 
-__device__ uint64_t memo_index_g(const DevGraph *g, uint32_t T) {
+__device__ __forceinline__ uint64_t memo_index_t(const uint32_t *binom, const uint64_t *loff, uint32_t T) {
     uint32_t r = 0;
     int i = 1;
-    for (uint32_t U = T; U; U &= U - 1, ++i) r += g->lds.binom[ctz32(U) * 33 + i];
-    return g->lds.loff[i - 1] + r;
+    for (uint32_t U = T; U; U &= U - 1, ++i) r += binom[ctz32(U) * 33 + i];
+    return loff[i - 1] + r;
 }
 
 // Rebuild the plan (Section 5: fetched recursively through left/right) in
-// post-order on one thread; n - 1 memo reads.
-__global__ void k_extract(const DevGraph *g, uint32_t n, MemoPtrs M, mpdp_plan_node *plan, double *root_cost,
-                          Counters *cnt) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (uint32_t v = 0; v < n; ++v) {
-        const uint64_t at = g->lds.loff[1] + v;
+// post-order.  Lane 0 follows the left pointers (the only dependent chain,
+// n - 1 reads); then the wave fills cost, card and operator of all nodes.
+__global__ __launch_bounds__(64) void k_extract(const DevGraph *g, uint32_t n, MemoPtrs M, mpdp_plan_node *plan,
+                                                double *root_cost, Counters *cnt) {
+    __shared__ uint32_t binom[33 * 33];
+    __shared__ uint64_t loff[34];
+    __shared__ uint32_t node_set[64];
+    __shared__ int node_l[64], node_r[64];
+    __shared__ int node_count;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < 33 * 33; i += blockDim.x) binom[i] = g->lds.binom[i];
+    if (t < 34) loff[t] = g->lds.loff[t];
+    __syncthreads();
+    const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    if (t == 0) {
+        int next = (int)n;
+        if (n > 1) {
+            struct Frame { uint32_t S; uint32_t L; int stage; int li; };
+            Frame st[33];
+            int sp = 0, ret = -1, guard = 0;
+            st[sp++] = Frame{full, M.left[memo_index_t(binom, loff, full)], 0, -1};
+            while (sp > 0 && ++guard < 4 * 64) {
+                Frame &f = st[sp - 1];
+                const uint32_t Lft = f.L;
+                if (Lft == 0 || (Lft & ~f.S) != 0 || Lft == f.S) { cnt->extract_error = 1; next = -1; break; }
+                const uint32_t Rgt = f.S & ~Lft;
+                if (f.stage == 0) {
+                    f.stage = 1;
+                    if ((Lft & (Lft - 1)) == 0) ret = ctz32(Lft);
+                    else {
+                        if (sp >= 33) { cnt->extract_error = 2; next = -1; break; }
+                        st[sp++] = Frame{Lft, M.left[memo_index_t(binom, loff, Lft)], 0, -1};
+                        continue;
+                    }
+                }
+                if (f.stage == 1) {
+                    f.li = ret;
+                    f.stage = 2;
+                    if ((Rgt & (Rgt - 1)) == 0) ret = ctz32(Rgt);
+                    else {
+                        if (sp >= 33) { cnt->extract_error = 2; next = -1; break; }
+                        st[sp++] = Frame{Rgt, M.left[memo_index_t(binom, loff, Rgt)], 0, -1};
+                        continue;
+                    }
+                }
+                if (next >= 63) { cnt->extract_error = 3; next = -1; break; }
+                node_set[next] = f.S;
+                node_l[next] = f.li;
+                node_r[next] = ret;
+                ret = next++;
+                --sp;
+            }
+            if (next >= 0 && (sp != 0 || next != (int)(2 * n - 1))) { cnt->extract_error = 3; next = -1; }
+        }
+        node_count = next;
+        *root_cost = M.cost[memo_index_t(binom, loff, full)];
+    }
+    __syncthreads();
+    const int total = node_count;
+    if (total < 0) return;
+    for (uint32_t v = t; v < n; v += blockDim.x) {
+        const uint64_t at = loff[1] + v;
         plan[v] = mpdp_plan_node{-1, -1, 1u << v, MPDP_OP_SCAN, M.cost[at], M.card[at]};
     }
-    const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
-    *root_cost = M.cost[memo_index_g(g, full)];
-    if (n == 1) return;
-    struct Frame { uint32_t S; uint32_t L; int stage; int li; };
-    Frame st[33];
-    int sp = 0, next = (int)n, ret = -1, guard = 0;
-    st[sp++] = Frame{full, M.left[memo_index_g(g, full)], 0, -1};
-    while (sp > 0 && ++guard < 4 * 64) {
-        Frame &f = st[sp - 1];
-        const uint32_t Lft = f.L;
-        if (Lft == 0 || (Lft & ~f.S) != 0 || Lft == f.S) { cnt->extract_error = 1; return; }
-        const uint32_t Rgt = f.S & ~Lft;
-        if (f.stage == 0) {
-            f.stage = 1;
-            if ((Lft & (Lft - 1)) == 0) ret = ctz32(Lft);
-            else {
-                if (sp >= 33) { cnt->extract_error = 2; return; }
-                st[sp++] = Frame{Lft, M.left[memo_index_g(g, Lft)], 0, -1};
-                continue;
-            }
-        }
-        if (f.stage == 1) {
-            f.li = ret;
-            f.stage = 2;
-            if ((Rgt & (Rgt - 1)) == 0) ret = ctz32(Rgt);
-            else {
-                if (sp >= 33) { cnt->extract_error = 2; return; }
-                st[sp++] = Frame{Rgt, M.left[memo_index_g(g, Rgt)], 0, -1};
-                continue;
-            }
-        }
-        const uint64_t at = memo_index_g(g, f.S);
-        plan[next] = mpdp_plan_node{f.li, ret, f.S, (uint32_t)M.op[at], M.cost[at], M.card[at]};
-        ret = next++;
-        --sp;
+    for (int j = (int)n + (int)t; j < total; j += (int)blockDim.x) {
+        const uint64_t at = memo_index_t(binom, loff, node_set[j]);
+        plan[j] = mpdp_plan_node{node_l[j], node_r[j], node_set[j], (uint32_t)M.op[at], M.cost[at], M.card[at]};
     }
-    if (sp != 0 || next != (int)(2 * n - 1)) cnt->extract_error = 3;
 }
 
 uint32_t grid_for(uint64_t items, uint64_t per_block) {
