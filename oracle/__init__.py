@@ -211,3 +211,56 @@ def plan_from_memo(memo: Memo) -> list[dict]:
 
     rec(memo.full)
     return nodes
+
+
+def induced(q, S: int):
+    """The sub-query on the relations of S, relabelled in increasing order.
+    The relabelling keeps the order of relations, so card(), the cost
+    formulas and the left-bitmap tie-break give the same values for subsets
+    of S: the sub-query's root entry equals the full query's memo entry of S."""
+    from paper_2202_13511_amd.workloads import Query
+    rel = [v for v in range(q.n) if S >> v & 1]
+    pos = {v: i for i, v in enumerate(rel)}
+    keep = [i for i, (u, v) in enumerate(q.edges.tolist()) if u in pos and v in pos]
+    e = np.array([[pos[int(q.edges[i, 0])], pos[int(q.edges[i, 1])]] for i in keep], np.uint32).reshape(-1, 2)
+    return Query(len(rel), e, q.card[rel].copy(), q.sel[keep].copy(), f"{q.name}[{S:#x}]"), rel
+
+
+def expand(rel, local: int) -> int:
+    """Map a relation set of an induced sub-query back to the full query."""
+    out = 0
+    for i, v in enumerate(rel):
+        if local >> i & 1:
+            out |= 1 << v
+    return out
+
+
+def recost_plan(q, plan, cost_model):
+    """Cost of a plan (list of mpdp_plan_node-like dicts: leaves first, root
+    last) recomputed bottom-up from its own nodes with card() and the written
+    cost definitions; also checks every join node joins a csg-cmp pair."""
+    cost, crd = {}, {}
+    for i, nd in enumerate(plan):
+        if nd["left"] < 0:
+            v = nd["relset"].bit_length() - 1
+            cost[i] = 0.01 * float(q.card[v]) if cost_model == COST_PGLIKE else 0.0
+            crd[i] = float(q.card[v])
+            continue
+        a, b = nd["left"], nd["right"]
+        L, R = plan[a]["relset"], plan[b]["relset"]
+        if L & R or (L | R) != nd["relset"]:
+            raise ValueError("children do not partition the node")
+        for X in (L, R):
+            if grow(q, X & -X, X) != X:
+                raise ValueError("child not connected")
+        if grow(q, L, L | R) != L | R:
+            raise ValueError("children not adjacent")
+        cS = card(q, nd["relset"])
+        crd[i] = cS
+        if cost_model == COST_COUT:
+            cost[i] = (cost[a] + cost[b]) + cS
+        elif nd["op"] == OP_HASH:
+            cost[i] = (((cost[a] + cost[b]) + 0.0125 * crd[b]) + 0.0025 * crd[a]) + 0.01 * cS
+        else:
+            cost[i] = ((cost[a] + cost[b]) + (0.0025 * crd[a]) * crd[b]) + 0.01 * cS
+    return cost[len(plan) - 1]

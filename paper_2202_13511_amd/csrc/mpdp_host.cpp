@@ -30,7 +30,7 @@ uint64_t binom64(uint32_t a, uint32_t b) {
 }
 
 struct Layout {
-    size_t cost, card, left, op, list, graph, counters, plan, root, total;
+    size_t cost, card, left, op, list, heavy, graph, counters, plan, root, total;
 };
 
 Layout make_layout(uint32_t n) {
@@ -42,6 +42,7 @@ Layout make_layout(uint32_t n) {
     L.left = o;     o = align_up(o + 4 * N);
     L.op = o;       o = align_up(o + N);
     L.list = o;     o = align_up(o + 4 * binom64(n, n / 2));
+    L.heavy = o;    o = align_up(o + 4 * binom64(n, n / 2));
     L.graph = o;    o = align_up(o + sizeof(DevGraph));
     L.counters = o; o = align_up(o + sizeof(Counters));
     L.plan = o;     o = align_up(o + sizeof(mpdp_plan_node) * 64);
@@ -192,6 +193,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     MemoPtrs memo{reinterpret_cast<double *>(base + L.cost), reinterpret_cast<double *>(base + L.card),
                   reinterpret_cast<uint32_t *>(base + L.left), reinterpret_cast<uint8_t *>(base + L.op)};
     uint32_t *list = reinterpret_cast<uint32_t *>(base + L.list);
+    uint32_t *heavy = reinterpret_cast<uint32_t *>(base + L.heavy);
     DevGraph *dg = reinterpret_cast<DevGraph *>(base + L.graph);
     Counters *cnt = reinterpret_cast<Counters *>(base + L.counters);
     mpdp_plan_node *dplan = reinterpret_cast<mpdp_plan_node *>(base + L.plan);
@@ -213,7 +215,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         if (general) HIPCHK(mpdp::launch_filter(dg, k, nc, list, cnt, s));
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 7], s));
         if (general)
-            HIPCHK(mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, cnt, memo, s));
+            HIPCHK(mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, heavy, cnt, memo, s));
         else  // tree joins: unrank, filter and evaluate in one kernel per level
             HIPCHK(mpdp::launch_level_tree(dg, q.cost_model, k, nc, cnt, memo, s));
         ++launches;

@@ -51,6 +51,7 @@ struct MemoPtrs {
 // Device-side counters, cleared by the init kernel.
 struct Counters {
     uint32_t level_count[34];   // connected sets found at each level
+    uint32_t heavy_count[34];   // sets handed to the heavy kernel at each level
     uint32_t extract_error;     // nonzero if plan extraction met an inconsistent memo
     uint32_t pad;
     unsigned long long evaluated; // Alg. 3 candidates (general path)
@@ -63,7 +64,7 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
 hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
                              MemoPtrs memo, hipStream_t s);
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
-                               const uint32_t *list, Counters *cnt, MemoPtrs memo, hipStream_t s);
+                               const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, hipStream_t s);
 hipError_t launch_extract(const DevGraph *g, uint32_t n, MemoPtrs memo, mpdp_plan_node *plan,
                           double *root_cost, Counters *cnt, hipStream_t s);
 

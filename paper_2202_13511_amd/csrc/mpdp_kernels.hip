@@ -28,6 +28,8 @@ constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tre
 constexpr int kRing = 384;          // per-wave ring of connected sets (>= 63 + 64 * kTreeChunkMax)
 constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
 constexpr int kEvalChunk = 16;      // block-local candidates per lane chunk
+constexpr uint32_t kHeavyChunks = 256;   // above this many chunks a set goes to k_eval_heavy
+constexpr int kHeavyBlock = 1024;        // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
 
 static_assert(kRing >= 63 + 64 * kTreeChunkMax, "ring too small");
@@ -418,18 +420,157 @@ struct WaveScratch {
     uint32_t cpre[33];   // prefix of candidate chunks per block
 };
 
-// Alg. 3: one wave64 per connected set S.
-//  1. cut vertices of G[S]: lane v checks whether G[S - v] is connected;
-//  2. blocks: split S at a cut vertex into pieces {x} + component, and
-//     split pieces again until a piece has no cut vertex of its own;
-//  3. lanes share the block-local candidates lb (lb holds the block's lowest
-//     relation, lb != block, so each unordered pair is visited once and both
-//     orientations are costed); a candidate is a pair when G[lb] and G[rb]
-//     are connected; then S_left = grow(lb, S - rb), S_right = S - S_left;
-//  4. wave min-reduce of the plan key, lane 0 writes the memo.
+struct SetBlocks {
+    uint32_t A;             // cut vertices of G[S]
+    uint32_t total_chunks;  // candidate chunks over all blocks
+    unsigned long long evaluated;  // Alg. 3 candidates of S: sum over blocks of 2^b - 2
+};
+
+// Blocks of G[S] for one connected S, computed by one wave:
+//  1. cut vertices: lane v checks whether G[S - v] is connected;
+//  2. split S at a cut vertex into pieces {x} + component, and split pieces
+//     again until a piece has no cut vertex of its own.  A piece is a union
+//     of blocks of S; its attachment set holds the split vertices it still
+//     contains, which are not cut vertices of the piece, while every other
+//     cut vertex of S inside the piece is.  Control flow is uniform; the
+//     piece stack lives one entry per lane.
+// The block list, completeness flags and candidate-chunk prefix go to W.
+__device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, int lane) {
+    // degrees in G[S]; a connected S with |S| - 1 edges induces a tree, whose
+    // blocks are its edges and whose cut vertices are its inner relations
+    const bool mine = lane < 32 && ((S >> lane) & 1u);
+    const uint32_t deg = mine ? (uint32_t)popc32(L.adj[lane] & S) : 0u;
+    uint32_t edges2 = deg;
+    for (int off = 32; off >= 1; off >>= 1) edges2 += (uint32_t)__shfl_xor((int)edges2, off);
+    const int kS = popc32(S);
+    if (edges2 == 2u * (uint32_t)(kS - 1)) {
+        const uint32_t A = (uint32_t)__ballot(mine && deg >= 2);
+        // lane v owns the edges to its smaller neighbours in S
+        const uint32_t lower = mine ? (L.adj[lane] & S & ((1u << lane) - 1u)) : 0u;
+        const uint32_t cnt = (uint32_t)popc32(lower);
+        uint32_t before = 0;
+        for (int b = 0; b < 5; ++b)
+            before += (uint32_t)__popcll(__ballot((cnt >> b) & 1u) & ((1ull << lane) - 1ull)) << b;
+        uint32_t at = before;
+        for (uint32_t U = lower; U; U &= U - 1, ++at) {
+            W.blk[at] = lowbit(U) | (1u << lane);
+            W.full[at] = 1;
+            W.cpre[at] = at;
+        }
+        if (lane == 0) W.cpre[kS - 1] = (uint32_t)(kS - 1);
+        return SetBlocks{A, (uint32_t)(kS - 1), 2ull * (unsigned long long)(kS - 1)};
+    }
+
+    bool cut = false;
+    if (mine) {
+        const uint32_t R = S & ~(1u << lane);
+        cut = grow(L.nb, lowbit(R), R) != R;
+    }
+    const uint32_t A = (uint32_t)__ballot(cut);
+
+    uint32_t stkP = 0, stkA = 0, myblk = 0;
+    int sp = 0, nblk = 0, steps = 0;
+    if (lane == 0) { stkP = S; stkA = 0; }
+    sp = 1;
+    while (sp > 0 && steps < 2 * kMaxRel) {
+        ++steps;
+        --sp;
+        const uint32_t P = rdlane(stkP, sp);
+        const uint32_t at = rdlane(stkA, sp);
+        const uint32_t cuts = A & P & ~at;
+        if (cuts == 0) {
+            if (lane == nblk) myblk = P;
+            nblk += nblk < kMaxRel - 1 ? 1 : 0;
+            continue;
+        }
+        const uint32_t x = lowbit(cuts);
+        uint32_t rem = P & ~x;
+        while (rem) {
+            const uint32_t K = grow(L.nb, lowbit(rem), rem);
+            rem &= ~K;
+            if (lane == sp) { stkP = K | x; stkA = (at | x) & (K | x); }
+            sp += sp < 63 ? 1 : 0;
+        }
+    }
+
+    // per-block candidate counts (lane i owns block i)
+    uint32_t chunks = 0, complete = 0;
+    if (lane < nblk) {
+        const int bs = popc32(myblk);
+        const uint32_t half = (1u << (bs - 1)) - 1u;
+        chunks = (half + kEvalChunk - 1) / kEvalChunk;
+        uint32_t deg = 0;
+        for (uint32_t T = myblk; T; T &= T - 1) deg += popc32(L.adj[ctz32(T)] & myblk);
+        complete = deg == (uint32_t)(bs * (bs - 1));
+    }
+    uint32_t acc = 0, mypre = 0;
+    unsigned long long evaluated = 0;
+    for (int i = 0; i < nblk; ++i) {
+        const uint32_t c = rdlane(chunks, i);
+        if (lane == i) mypre = acc;
+        acc += c;
+        evaluated += (1ull << popc32(rdlane(myblk, i))) - 2ull;
+    }
+    if (lane < nblk) { W.blk[lane] = myblk; W.full[lane] = complete; W.cpre[lane] = mypre; }
+    if (lane == 0) W.cpre[nblk] = acc;
+    return SetBlocks{A, acc, evaluated};
+}
+
+// Colex ranks of Sl and of S - Sl in one pass over the members of S.
+__device__ __forceinline__ void split_ranks(const LdsGraph &L, uint32_t S, uint32_t Sl, uint32_t &rl, uint32_t &rr) {
+    uint32_t a = 0, b = 0;
+    int il = 1, ir = 1;
+    for (uint32_t T = S; T; T &= T - 1) {
+        const int v = ctz32(T);
+        if ((Sl >> v) & 1u) a += L.binom[v * 33 + il++];
+        else b += L.binom[v * 33 + ir++];
+    }
+    rl = a;
+    rr = b;
+}
+
+// Alg. 3 candidates of the chunks ch = first, first + stride, ... of S: for
+// each block-local lb holding the block's lowest relation (lb != block, so
+// each unordered pair is met once and both orientations are costed) the CCP
+// check is that G[lb] and G[rb] are connected (they are adjacent because the
+// block is); then S_left = grow(lb, S - rb) and S_right = S - S_left.
+template <int CM>
+__device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M, const WaveScratch &W, uint32_t S,
+                                            uint32_t A, uint32_t total_chunks, uint32_t first, uint32_t stride,
+                                            double cardS, Key &best, unsigned long long &ccp) {
+    const int k = popc32(S);
+    for (uint32_t ch = first; ch < total_chunks; ch += stride) {
+        int bi = 0;
+        while (W.cpre[bi + 1] <= ch) ++bi;
+        const uint32_t b = W.blk[bi];
+        const bool full = W.full[bi] != 0;
+        const uint32_t lo = lowbit(b), rest = b ^ lo;
+        const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
+        const uint32_t j0 = (ch - W.cpre[bi]) * kEvalChunk;
+        const uint32_t j1 = min(j0 + (uint32_t)kEvalChunk, hb);
+        uint32_t sub = deposit(j0, rest);
+        for (uint32_t j = j0; j < j1; ++j) {
+            const uint32_t lb = lo | sub, rb = b ^ lb;
+            sub = (sub - rest) & rest;
+            if (!full) {
+                if (grow(L.nb, lo, lb) != lb) continue;
+                if (grow(L.nb, lowbit(rb), rb) != rb) continue;
+            }
+            ++ccp;
+            const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
+            uint32_t rl, rr;
+            split_ranks(L, S, Sl, rl, rr);
+            const int kl = popc32(Sl);
+            eval_pair<CM>(M, Sl, S ^ Sl, L.loff[kl] + rl, L.loff[k - kl] + rr, cardS, best);
+        }
+    }
+}
+
+// Alg. 3, light sets: one wave64 per connected S.  A set with more than
+// kHeavyChunks candidate chunks is handed to k_eval_heavy instead.
 template <int CM>
 __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint32_t k, const uint32_t *list,
-                                                         Counters *cnt, MemoPtrs M) {
+                                                         uint32_t *heavy, Counters *cnt, MemoPtrs M) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ WaveScratch WS[kWaves];
     stage_graph(g, L);
@@ -440,97 +581,70 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
 
     for (uint32_t idx = blockIdx.x * kWaves + (threadIdx.x >> 6); idx < count; idx += gridDim.x * kWaves) {
         const uint32_t S = list[idx];
-
-        // 1. cut vertices
-        bool cut = false;
-        if (lane < 32 && ((S >> lane) & 1u)) {
-            const uint32_t R = S & ~(1u << lane);
-            cut = grow(L.nb, lowbit(R), R) != R;
+        const SetBlocks sb = analyze_set(L, S, W, lane);
+        if (sb.total_chunks > kHeavyChunks) {
+            if (lane == 0) heavy[atomicAdd(&cnt->heavy_count[k], 1u)] = S;
+            wave_sync_lds();
+            continue;
         }
-        const uint32_t A = (uint32_t)__ballot(cut);
-
-        // 2. blocks (uniform control flow; the stack lives one entry per lane).
-        // A piece is a union of blocks of S; its attachment set holds the
-        // split vertices it still contains, which are not cut vertices of
-        // the piece.  Every other cut vertex of S inside the piece is.
-        uint32_t stkP = 0, stkA = 0, myblk = 0;
-        int sp = 0, nblk = 0, steps = 0;
-        if (lane == 0) { stkP = S; stkA = 0; }
-        sp = 1;
-        while (sp > 0 && steps < 2 * kMaxRel) {
-            ++steps;
-            --sp;
-            const uint32_t P = rdlane(stkP, sp);
-            const uint32_t at = rdlane(stkA, sp);
-            const uint32_t cuts = A & P & ~at;
-            if (cuts == 0) {
-                if (lane == nblk) myblk = P;
-                nblk += nblk < kMaxRel - 1 ? 1 : 0;
-                continue;
-            }
-            const uint32_t x = lowbit(cuts);
-            uint32_t rem = P & ~x;
-            while (rem) {
-                const uint32_t K = grow(L.nb, lowbit(rem), rem);
-                rem &= ~K;
-                if (lane == sp) { stkP = K | x; stkA = (at | x) & (K | x); }
-                sp += sp < 63 ? 1 : 0;
-            }
-        }
-
-        // 3. per-block candidate counts (lane i owns block i)
-        uint32_t chunks = 0, complete = 0;
-        if (lane < nblk) {
-            const int bs = popc32(myblk);
-            const uint32_t half = (1u << (bs - 1)) - 1u;
-            chunks = (half + kEvalChunk - 1) / kEvalChunk;
-            uint32_t deg = 0;
-            for (uint32_t T = myblk; T; T &= T - 1) deg += popc32(L.adj[ctz32(T)] & myblk);
-            complete = deg == (uint32_t)(bs * (bs - 1));
-        }
-        uint32_t acc = 0, mypre = 0;
-        for (int i = 0; i < nblk; ++i) {
-            const uint32_t c = rdlane(chunks, i);
-            if (lane == i) mypre = acc;
-            acc += c;
-            my_eval += (lane == 0) ? (1ull << popc32(rdlane(myblk, i))) - 2ull : 0ull;
-        }
-        const uint32_t total_chunks = acc;
-        if (lane < nblk) { W.blk[lane] = myblk; W.full[lane] = complete; W.cpre[lane] = mypre; }
-        if (lane == 0) W.cpre[nblk] = total_chunks;
+        if (lane == 0) my_eval += sb.evaluated;
         wave_sync_lds();
-
         const double cardS = card_of(L, S);
         Key best = worst_key();
-        for (uint32_t ch = lane; ch < total_chunks; ch += 64) {
-            int bi = 0;
-            while (W.cpre[bi + 1] <= ch) ++bi;
-            const uint32_t b = W.blk[bi];
-            const bool full = W.full[bi] != 0;
-            const uint32_t lo = lowbit(b), rest = b ^ lo;
-            const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
-            const uint32_t j0 = (ch - W.cpre[bi]) * kEvalChunk;
-            const uint32_t j1 = min(j0 + (uint32_t)kEvalChunk, hb);
-            uint32_t sub = deposit(j0, rest);
-            for (uint32_t j = j0; j < j1; ++j) {
-                const uint32_t lb = lo | sub, rb = b ^ lb;
-                sub = (sub - rest) & rest;
-                if (!full) {
-                    if (grow(L.nb, lo, lb) != lb) continue;
-                    if (grow(L.nb, lowbit(rb), rb) != rb) continue;
-                }
-                ++my_ccp;
-                const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
-                const uint32_t Sr = S ^ Sl;
-                eval_pair<CM>(M, Sl, Sr, memo_index(L, Sl), memo_index(L, Sr), cardS, best);
-            }
-        }
+        eval_chunks<CM>(L, M, W, S, sb.A, sb.total_chunks, (uint32_t)lane, 64u, cardS, best, my_ccp);
         best = wave_min(best);
         if (lane == 0) store_best(M, memo_index(L, S), best, cardS);
         wave_sync_lds();
     }
 
     // one atomic per wave for the counters
+    for (int off = 32; off >= 1; off >>= 1) {
+        my_ccp += (unsigned long long)__shfl_xor((long long)my_ccp, off);
+        my_eval += (unsigned long long)__shfl_xor((long long)my_eval, off);
+    }
+    if (lane == 0 && (my_ccp || my_eval)) {
+        atomicAdd(&cnt->ccp, my_ccp);
+        atomicAdd(&cnt->evaluated, my_eval);
+    }
+}
+
+// Alg. 3, heavy sets: one 1024-thread workgroup per set.  Wave 0 finds the
+// blocks, all 16 waves share the candidate chunks, and the plan keys are
+// reduced through LDS.
+template <int CM>
+__global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, uint32_t k, const uint32_t *heavy,
+                                                            Counters *cnt, MemoPtrs M) {
+    constexpr int kHW = kHeavyBlock / 64;
+    __shared__ __align__(16) LdsGraph L;
+    __shared__ WaveScratch W;
+    __shared__ SetBlocks sbs;
+    __shared__ Key keys[kHW];
+    stage_graph(g, L);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t count = cnt->heavy_count[k];
+    unsigned long long my_ccp = 0, my_eval = 0;
+    for (uint32_t h = blockIdx.x; h < count; h += gridDim.x) {
+        const uint32_t S = heavy[h];
+        if (wave == 0) {
+            const SetBlocks sb = analyze_set(L, S, W, lane);
+            if (lane == 0) { sbs = sb; my_eval += sb.evaluated; }
+        }
+        __syncthreads();
+        const SetBlocks sb = sbs;
+        const double cardS = card_of(L, S);
+        Key best = worst_key();
+        eval_chunks<CM>(L, M, W, S, sb.A, sb.total_chunks, threadIdx.x, kHeavyBlock, cardS, best, my_ccp);
+        best = wave_min(best);
+        if (lane == 0) keys[wave] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Key b = keys[0];
+            for (int i = 1; i < kHW; ++i)
+                if (key_less(keys[i], b)) b = keys[i];
+            store_best(M, memo_index(L, S), b, cardS);
+        }
+        __syncthreads();
+    }
     for (int off = 32; off >= 1; off >>= 1) {
         my_ccp += (unsigned long long)__shfl_xor((long long)my_ccp, off);
         my_eval += (unsigned long long)__shfl_xor((long long)my_eval, off);
@@ -664,12 +778,23 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
 }
 
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
-                               const uint32_t *list, Counters *cnt, MemoPtrs memo, hipStream_t s) {
+                               const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, hipStream_t s) {
     const uint32_t grid = grid_for(ncand, kWaves);
     if (cost_model == MPDP_COST_COUT)
-        hipLaunchKernelGGL(k_eval_general<MPDP_COST_COUT>, dim3(grid), dim3(kBlock), 0, s, g, k, list, cnt, memo);
+        hipLaunchKernelGGL(k_eval_general<MPDP_COST_COUT>, dim3(grid), dim3(kBlock), 0, s, g, k, list, heavy, cnt,
+                           memo);
     else
-        hipLaunchKernelGGL(k_eval_general<MPDP_COST_PGLIKE>, dim3(grid), dim3(kBlock), 0, s, g, k, list, cnt,
+        hipLaunchKernelGGL(k_eval_general<MPDP_COST_PGLIKE>, dim3(grid), dim3(kBlock), 0, s, g, k, list, heavy, cnt,
+                           memo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // heavy sets: at most one per workgroup at a time, two workgroups per CU
+    const uint64_t hgrid64 = ncand < 512 ? (ncand ? ncand : 1) : 512;
+    const uint32_t hgrid = (uint32_t)hgrid64;
+    if (cost_model == MPDP_COST_COUT)
+        hipLaunchKernelGGL(k_eval_heavy<MPDP_COST_COUT>, dim3(hgrid), dim3(kHeavyBlock), 0, s, g, k, heavy, cnt, memo);
+    else
+        hipLaunchKernelGGL(k_eval_heavy<MPDP_COST_PGLIKE>, dim3(hgrid), dim3(kHeavyBlock), 0, s, g, k, heavy, cnt,
                            memo);
     return hipGetLastError();
 }

@@ -11,8 +11,12 @@ Workloads (generators in paper_2202_13511_amd.workloads):
   star25      hub + 24 leaves, seeds 0..15, C_out and PG-like
   snowflake25 depth 3, fanout U{2..4}, seeds 0..63 C_out, 0..15 PG-like
   clique18    seeds 0..31, C_out
-  cycle       ring of U{20..30} + U{5..15} chords, seeds 0..31, C_out, kept
-              when n <= 22 (larger ones exceed the oracle's time budget)
+  cycle       ring of U{20..30} + U{5..15} chords, seeds 0..31, C_out: whole
+              query when n <= 22; for larger n (beyond the oracle's time
+              budget for a whole query) 16 connected sets per query drawn by
+              a seeded random walk, each solved by the oracle on its induced
+              sub-query (relabelled in increasing order, which leaves every
+              memo value unchanged)
 
 Usage: python tests/golden/make_oracle_golden.py [--jobs 8]
 """
@@ -61,12 +65,44 @@ def hexbits(x) -> str:
     return f"{int(np.float64(x).view(np.uint64)):016x}"
 
 
+def random_connected_set(q, rng, size):
+    adj = q.adjacency()
+    S = 1 << int(rng.integers(0, q.n))
+    while bin(S).count("1") < size:
+        frontier = 0
+        for v in range(q.n):
+            if S >> v & 1:
+                frontier |= adj[v]
+        frontier &= ~S
+        cand = [v for v in range(q.n) if frontier >> v & 1]
+        S |= 1 << cand[int(rng.integers(0, len(cand)))]
+    return S
+
+
+def sampled(q, kind, seed, cm):
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(2000 + seed))
+    samples = []
+    seen = set()
+    while len(samples) < 16:
+        S = random_connected_set(q, rng, int(rng.integers(3, 17)))
+        if S in seen:
+            continue
+        seen.add(S)
+        sub, rel = oracle.induced(q, S)
+        m = oracle.mpdp(sub, cm)
+        samples.append([int(S), hexbits(m.root_cost), hexbits(m.card[m.full]),
+                        oracle.expand(rel, int(m.left[m.full])), int(m.op[m.full])])
+    return {"kind": kind, "n": q.n, "seed": seed, "cost_model": cm, "name": q.name, "m": q.m,
+            "sampled_only": True, "samples": samples}
+
+
 def one(spec):
     import oracle
     kind, n, seed, cm = spec
     q = make_query(kind, n, seed)
     if kind == "cycle_chords" and q.n > 22:
-        return None
+        return sampled(q, kind, seed, cm)
     m = oracle.mpdp(q, cm)
     tree = q.m == q.n - 1
     evaluated = m.evaluated if not tree else m.ccp_ordered

@@ -188,3 +188,35 @@ def test_tie_storm_is_deterministic():
     # with all statistics equal every split of S ties on cost; the smallest
     # left bitmap among the cheapest splits must be chosen
     assert int(a.left[(1 << 8) - 1]) & 1 == 1
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_induced_subquery_equals_memo_entry(cm):
+    """The full-size cyclic checks solve a set S on its own induced sub-query
+    (relations relabelled in increasing order).  That must reproduce the
+    whole query's memo entry of S bit for bit, left set and operator included."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    for q in [W.cycle_chords(3, n=14, chords=6), W.random_connected(13, 4, 0.3), W.snowflake(15, 1)]:
+        m = oracle.mpdp(q, cm)
+        mask = m.has_plan()
+        conn = np.nonzero(mask)[0]
+        conn = conn[conn & (conn - 1) != 0]
+        for S in rng.choice(conn, size=40, replace=False).tolist():
+            sub, rel = oracle.induced(q, S)
+            ms = oracle.mpdp(sub, cm)
+            assert ms.cost[ms.full] == m.cost[S] and ms.card[ms.full] == m.card[S]
+            assert oracle.expand(rel, int(ms.left[ms.full])) == m.left[S]
+            assert ms.op[ms.full] == m.op[S]
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_recost_plan_helper(cm):
+    for q in small_graphs()[:9]:
+        m = oracle.mpdp(q, cm)
+        plan = oracle.plan_from_memo(m)
+        assert oracle.recost_plan(q, plan, cm) == m.root_cost
+        # a join node whose children do not cover it is rejected
+        bad = [dict(nd) for nd in plan]
+        bad[-1]["right"] = bad[-1]["left"]
+        with pytest.raises(ValueError):
+            oracle.recost_plan(q, bad, cm)
