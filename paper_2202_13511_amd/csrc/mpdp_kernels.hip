@@ -62,8 +62,8 @@ __device__ __forceinline__ uint32_t grow(const uint32_t (*nb)[256], uint32_t sou
 
 // Next bitmap with the same popcount (next k-subset in colex order).
 __device__ __forceinline__ uint32_t next_subset(uint32_t x) {
-    uint32_t c = lowbit(x), r = x + c;
-    return (((r ^ x) >> 2) / c) | r;
+    const uint32_t r = x + lowbit(x);
+    return (((r ^ x) >> 2) >> ctz32(x)) | r;  // the divisor lowbit(x) is a power of two
 }
 
 // Spread the low bits of j over the set bits of mask (parallel bit deposit).
