@@ -149,6 +149,58 @@ mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges,
                              void *hip_stream, uint32_t flags, mpdp_plan_node *plan_out,
                              double *cost_out, mpdp_stats *stats_out);
 
+/*
+ * Batched optimization: many small queries in one launch.
+ *
+ * Query q has n relations whose cardinalities are
+ * cardinalities[card_offset .. card_offset + n) and m edges whose endpoints
+ * (0-based within the query) and selectivities are
+ * edges/selectivities[edge_offset .. edge_offset + m).  Every query obeys
+ * the rules of mpdp_optimize and has 1 <= n <= 20.
+ */
+typedef struct { uint32_t n, m, card_offset, edge_offset; } mpdp_batch_query;
+
+typedef struct {
+    uint64_t connected_sets;   /* summed over the batch (conventions as mpdp_stats) */
+    uint64_t evaluated_pairs;
+    uint64_t ccp_pairs;
+    double ms_total;           /* host wall time of the call                            */
+    double ms_kernel;          /* device time of the batch kernel (MPDP_FLAG_TIMING)      */
+    uint32_t workgroups;       /* persistent workgroups launched                        */
+    uint32_t max_n;            /* largest query in the batch                            */
+} mpdp_batch_stats;
+
+/* Device workspace bytes for mpdp_optimize_batch (0 if a query is invalid in
+ * size: n = 0 or n > 20).  It grows with the total input and output sizes
+ * and with min(nq, 512) memo slots of 2^max_n entries, not with nq itself. */
+size_t mpdp_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries);
+
+/*
+ * Optimize nq queries in one persistent launch on hip_stream: every
+ * workgroup takes the next query, runs all its DP levels with workgroup
+ * barriers between levels, and writes its plan.  Results equal those of
+ * mpdp_optimize on each query alone.
+ *   plans_out      host, sum over q of (2 n_q - 1) nodes; query q's plan
+ *                  (layout of mpdp_plan_node) starts after those of 0..q-1
+ *   costs_out      host, nq root costs
+ *   latency_us_out host, nullable: per query, microseconds from the start of
+ *                  the launch to the end of that query (device wall clock)
+ *   start_us_out   host, nullable: per query, microseconds from the start of
+ *                  the launch to the start of that query
+ *   stats_out      host, nullable
+ * Workgroups take the queries in order of decreasing size (more relations
+ * first, ties in input order), which shortens the tail of the launch.
+ * Validation is done on the host before any HIP call (MPDP_EINVAL,
+ * MPDP_ENOTCONNECTED, MPDP_ETOOLARGE name the first failing query's error);
+ * the call waits for hip_stream before returning.
+ */
+mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes,
+                                void *hip_stream, uint32_t flags, mpdp_plan_node *plans_out,
+                                double *costs_out, double *latency_us_out, double *start_us_out,
+                                mpdp_batch_stats *stats_out);
+
 #ifdef __cplusplus
 }
 #endif

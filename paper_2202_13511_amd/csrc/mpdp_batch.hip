@@ -1,0 +1,254 @@
+// Batched optimization of many small queries in one persistent launch.
+//
+// Each workgroup pulls the next query from an atomic counter and runs the
+// whole level loop of Alg. 5 for it, with workgroup barriers between levels
+// instead of kernel launches: it builds the query's LDS image from the raw
+// edges, cardinalities and selectivities, fills the base relations, runs
+// levels 2..n (Alg. 2 for tree joins, Alg. 3 otherwise: filter, one wave per
+// light set, the whole workgroup per heavy set), rebuilds the plan and
+// records the device wall clock at the query's start and end.  Memo and
+// scratch live in a per-workgroup slot that is reused from query to query,
+// so the workspace does not grow with the batch.
+#include <hip/hip_runtime.h>
+
+#include "mpdp_device.h"
+#include "mpdp_internal.h"
+
+namespace mpdp {
+namespace {
+
+constexpr int kBatchBlock = 512;
+constexpr int kBW = kBatchBlock / 64;
+
+// Build the LDS image of one query inside the workgroup (everything except
+// the binomials, which are staged once per workgroup).
+__device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t *edges, const double *cards,
+                            const double *sels) {
+    const uint32_t t = threadIdx.x, n = Q.n, m = Q.m;
+    const uint32_t *E = edges + 2ull * Q.edge_off;
+    const double *C = cards + Q.card_off;
+    const double *SL = sels + Q.edge_off;
+    if (t < kMaxRel) {
+        L.adj[t] = 0;
+        L.pbit[t] = 0;
+        L.desc[t] = 1u << t;
+        L.card[t] = t < n ? C[t] : 1.0;
+        L.bcost[t] = t < n ? (Q.cost_model == MPDP_COST_PGLIKE ? 0.01 * C[t] : 0.0) : 0.0;
+    }
+    __syncthreads();
+    for (uint32_t e = t; e < m; e += blockDim.x) {
+        const uint32_t u = E[2 * e], v = E[2 * e + 1];
+        atomicOr(&L.adj[u], 1u << v);
+        atomicOr(&L.adj[v], 1u << u);
+    }
+    __syncthreads();
+    if (t < n) {  // selectivities of edges (u, v), u < v, grouped by v, u ascending
+        const uint32_t lower = L.adj[t] & ((1u << t) - 1u);
+        uint32_t start = 0;
+        for (uint32_t w = 0; w < t; ++w) start += (uint32_t)popc32(L.adj[w] & ((1u << w) - 1u));
+        L.selrow[t] = start;
+        for (uint32_t e = 0; e < m; ++e) {
+            const uint32_t a = E[2 * e], b = E[2 * e + 1];
+            const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+            if (hi == t) L.sel[start + (uint32_t)popc32(lower & ((1u << lo) - 1u))] = SL[e];
+        }
+    }
+    for (uint32_t i = t; i < 4 * 256; i += blockDim.x) {
+        const uint32_t byte = i >> 8, x = i & 255u;
+        uint32_t u = 0;
+        for (uint32_t j = 0; j < 8; ++j)
+            if (((x >> j) & 1u) && 8u * byte + j < n) u |= L.adj[8u * byte + j];
+        L.nb[byte][x] = u;
+    }
+    if (t == 0) {
+        uint64_t off = 0;
+        for (uint32_t k = 0; k < 34; ++k) {
+            L.loff[k] = off;
+            if (k <= n) off += L.binom[n * 33 + k];
+        }
+        if (Q.is_tree) {  // rooted at relation 0: parent bits and subtree sets in BFS order
+            uint32_t order[kMaxRel], parent[kMaxRel];
+            uint32_t head = 0, tail = 0, vis = 1u;
+            order[tail++] = 0;
+            parent[0] = 0;
+            while (head < tail) {
+                const uint32_t v = order[head++];
+                for (uint32_t T = L.adj[v] & ~vis; T; T &= T - 1) {
+                    const uint32_t c = (uint32_t)ctz32(T);
+                    parent[c] = v;
+                    vis |= 1u << c;
+                    order[tail++] = c;
+                }
+            }
+            for (uint32_t i = 1; i < tail; ++i) L.pbit[order[i]] = 1u << parent[order[i]];
+            for (uint32_t i = tail - 1; i > 0; --i) L.desc[parent[order[i]]] |= L.desc[order[i]];
+        }
+    }
+    __syncthreads();
+}
+
+template <int CM>
+__global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, uint32_t nq, const uint32_t *edges,
+                                                       const double *cards, const double *sels,
+                                                       const uint32_t *binom_g, char *slots, uint64_t slot_bytes,
+                                                       uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
+                                                       BatchCounters *bc) {
+    __shared__ __align__(16) LdsGraph L;
+    __shared__ uint32_t rings[kBW][kRing];
+    __shared__ WaveScratch WS[kBW];
+    __shared__ SetBlocks hsb;
+    __shared__ Key hkeys[kBW];
+    __shared__ PlanScratch P;
+    __shared__ uint32_t s_q, s_count, s_hcount, s_level;
+    __shared__ unsigned long long s_conn, s_ccp, s_eval, s_t0;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    if (t == 0) atomicMin(&bc->t0, (unsigned long long)wall_clock64());
+    for (uint32_t i = t; i < 33 * 33; i += blockDim.x) L.binom[i] = binom_g[i];
+
+    // this workgroup's slot: memo (cost, card, left, op over 2^maxn entries), set list, heavy list
+    const uint64_t N = 1ull << maxn;
+    char *slot = slots + (uint64_t)blockIdx.x * slot_bytes;
+    MemoPtrs M{reinterpret_cast<double *>(slot), reinterpret_cast<double *>(slot + 8 * N),
+               reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
+    const uint64_t list_off = (21 * N + 255) & ~255ull;
+    uint32_t *list = reinterpret_cast<uint32_t *>(slot + list_off);
+    uint32_t *heavy = list + L.binom[maxn * 33 + maxn / 2];
+    (void)heavy;
+
+    for (;;) {
+        if (t == 0) s_q = atomicAdd(&bc->next, 1u);
+        __syncthreads();
+        const uint32_t q = s_q;
+        if (q >= nq) break;
+        const BatchQueryDev Q = qs[q];
+        build_image(L, Q, edges, cards, sels);
+        const uint32_t n = Q.n;
+        uint32_t *hv = list + L.binom[maxn * 33 + maxn / 2];
+        if (t == 0) {
+            s_t0 = (unsigned long long)wall_clock64();
+            s_conn = 0;
+            s_ccp = 0;
+            s_eval = 0;
+        }
+        if (t < n) {
+            const uint64_t at = L.loff[1] + t;
+            M.cost[at] = L.bcost[t];
+            M.card[at] = L.card[t];
+            M.left[at] = 0;
+            M.op[at] = MPDP_OP_SCAN;
+        }
+        __syncthreads();
+        unsigned long long my_ccp = 0, my_eval = 0;
+        for (uint32_t k = 2; k <= n; ++k) {
+            const uint64_t ncand = L.binom[n * 33 + k];
+            if (Q.is_tree) {
+                if (t == 0) s_level = 0;
+                __syncthreads();
+                const uint32_t found =
+                    level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, rings[wave], lane);
+                if (lane == 0 && found) atomicAdd(&s_level, found);
+                __syncthreads();
+                if (t == 0) {
+                    s_conn += s_level;
+                    s_ccp += (unsigned long long)(k - 1) * s_level;
+                    s_eval += 2ull * (k - 1) * s_level;
+                }
+                __syncthreads();
+                continue;
+            }
+            if (t == 0) { s_count = 0; s_hcount = 0; }
+            __syncthreads();
+            filter_wave(L, (int)n, k, ncand, wave, kBW, list, &s_count, lane);
+            __syncthreads();
+            const uint32_t count = s_count;
+            // light sets: one wave each
+            for (uint32_t idx = wave; idx < count; idx += kBW) {
+                const uint32_t S = list[idx];
+                const SetBlocks sb = analyze_set(L, S, WS[wave], lane);
+                if (sb.total_chunks > kHeavyChunks) {
+                    if (lane == 0) hv[atomicAdd(&s_hcount, 1u)] = S;
+                    wave_sync_lds();
+                    continue;
+                }
+                if (lane == 0) my_eval += sb.evaluated;
+                wave_sync_lds();
+                const double cardS = card_of(L, S);
+                Key best = worst_key();
+                eval_chunks<CM>(L, M, WS[wave], S, sb.A, sb.total_chunks, lane, 64u, cardS, best, my_ccp);
+                best = wave_min(best);
+                if (lane == 0) store_best(M, memo_index(L, S), best, cardS);
+                wave_sync_lds();
+            }
+            __syncthreads();
+            // heavy sets: the whole workgroup each
+            const uint32_t hcount = s_hcount;
+            for (uint32_t h = 0; h < hcount; ++h) {
+                const uint32_t S = hv[h];
+                if (wave == 0) {
+                    const SetBlocks sb = analyze_set(L, S, WS[0], lane);
+                    if (lane == 0) { hsb = sb; my_eval += sb.evaluated; }
+                }
+                __syncthreads();
+                const SetBlocks sb = hsb;
+                const double cardS = card_of(L, S);
+                Key best = worst_key();
+                eval_chunks<CM>(L, M, WS[0], S, sb.A, sb.total_chunks, t, blockDim.x, cardS, best, my_ccp);
+                best = wave_min(best);
+                if (lane == 0) hkeys[wave] = best;
+                __syncthreads();
+                if (t == 0) {
+                    Key b = hkeys[0];
+                    for (int i = 1; i < kBW; ++i)
+                        if (key_less(hkeys[i], b)) b = hkeys[i];
+                    store_best(M, memo_index(L, S), b, cardS);
+                }
+                __syncthreads();
+            }
+            if (t == 0) s_conn += count;
+            __syncthreads();
+        }
+        // counters of the block-based path
+        for (int off = 32; off >= 1; off >>= 1) {
+            my_ccp += (unsigned long long)__shfl_xor((long long)my_ccp, off);
+            my_eval += (unsigned long long)__shfl_xor((long long)my_eval, off);
+        }
+        if (lane == 0 && (my_ccp || my_eval)) {
+            atomicAdd(&s_ccp, my_ccp);
+            atomicAdd(&s_eval, my_eval);
+        }
+        __syncthreads();
+        double root = 0.0;
+        const bool ok = extract_plan(L.binom, L.loff, M, n, plans + Q.plan_off, &root, P, t, blockDim.x);
+        __syncthreads();
+        if (t == 0) {
+            BatchOut o;
+            o.cost = root;
+            o.t_start = s_t0;
+            o.t_end = (unsigned long long)wall_clock64();
+            o.connected = s_conn;
+            o.ccp = s_ccp;
+            o.evaluated = s_eval;
+            o.error = ok ? 0u : 1u;
+            o.pad = 0;
+            out[q] = o;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs, uint32_t nq,
+                        const uint32_t *edges, const double *cards, const double *sels, const uint32_t *binom,
+                        char *slots, uint64_t slot_bytes, uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
+                        BatchCounters *bc, hipStream_t s) {
+    if (cost_model == MPDP_COST_COUT)
+        hipLaunchKernelGGL(k_batch<MPDP_COST_COUT>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, nq, edges, cards,
+                           sels, binom, slots, slot_bytes, maxn, plans, out, bc);
+    else
+        hipLaunchKernelGGL(k_batch<MPDP_COST_PGLIKE>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, nq, edges,
+                           cards, sels, binom, slots, slot_bytes, maxn, plans, out, bc);
+    return hipGetLastError();
+}
+
+}  // namespace mpdp

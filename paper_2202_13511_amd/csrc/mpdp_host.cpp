@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <vector>
 
 #include "mpdp.h"
@@ -272,9 +273,194 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
 // Internal flag for tests: run Alg. 3 (the general kernel) on tree joins too.
 constexpr uint32_t kFlagForceGeneral = 0x100u;
 
+// ---------------------------------------------------------------- batch
+
+struct BatchLayout {
+    size_t binom, counters, queries, edges, cards, sels, plans, out, slots, slot_bytes, total;
+    uint32_t workgroups, maxn;
+    uint64_t sum_m, sum_n, sum_nodes;
+};
+
+bool batch_layout(uint32_t nq, const mpdp_batch_query *qs, BatchLayout &B) {
+    B = BatchLayout{};
+    if (nq == 0 || !qs) return false;
+    uint32_t maxn = 1;
+    for (uint32_t i = 0; i < nq; ++i) {
+        if (qs[i].n == 0 || qs[i].n > mpdp::kBatchMaxRel) return false;
+        maxn = qs[i].n > maxn ? qs[i].n : maxn;
+        B.sum_m += qs[i].m;
+        B.sum_n += qs[i].n;
+        B.sum_nodes += 2ull * qs[i].n - 1;
+    }
+    B.maxn = maxn;
+    B.workgroups = nq < mpdp::kBatchWorkgroups ? nq : mpdp::kBatchWorkgroups;
+    size_t o = 0;
+    B.binom = o;    o = align_up(o + 33 * 33 * 4);
+    B.counters = o; o = align_up(o + sizeof(mpdp::BatchCounters));
+    B.queries = o;  o = align_up(o + sizeof(mpdp::BatchQueryDev) * nq);
+    B.edges = o;    o = align_up(o + 8 * B.sum_m);
+    B.cards = o;    o = align_up(o + 8 * B.sum_n);
+    B.sels = o;     o = align_up(o + 8 * B.sum_m);
+    B.plans = o;    o = align_up(o + sizeof(mpdp_plan_node) * B.sum_nodes);
+    B.out = o;      o = align_up(o + sizeof(mpdp::BatchOut) * nq);
+    const uint64_t N = 1ull << maxn;
+    B.slot_bytes = align_up(21 * N) + align_up(8 * binom64(maxn, maxn / 2));
+    B.slots = o;    o += B.slot_bytes * B.workgroups;
+    B.total = align_up(o);
+    return true;
+}
+
+// Host validation of one batch query (same rules as mpdp_optimize).
+mpdp_status validate_batch_query(const mpdp_batch_query &Q, const mpdp_edge *edges, const double *card,
+                                 const double *sel) {
+    const uint32_t n = Q.n, m = Q.m;
+    if (n == 0) return MPDP_EINVAL;
+    if (n > mpdp::kBatchMaxRel) return MPDP_ETOOLARGE;
+    if (m > n * (n - 1) / 2) return MPDP_EINVAL;
+    uint32_t adj[32] = {0};
+    for (uint32_t v = 0; v < n; ++v) {
+        const double c = card[Q.card_offset + v];
+        if (!std::isfinite(c) || !(c >= 1.0)) return MPDP_EINVAL;
+    }
+    for (uint32_t i = 0; i < m; ++i) {
+        const mpdp_edge e = edges[Q.edge_offset + i];
+        const double s = sel[Q.edge_offset + i];
+        if (e.u >= n || e.v >= n || e.u == e.v) return MPDP_EINVAL;
+        if (adj[e.u] & (1u << e.v)) return MPDP_EINVAL;
+        if (!std::isfinite(s) || !(s > 0.0) || !(s <= 1.0)) return MPDP_EINVAL;
+        adj[e.u] |= 1u << e.v;
+        adj[e.v] |= 1u << e.u;
+    }
+    const uint32_t full = (1u << n) - 1u;
+    uint32_t seen = 1u, frontier = 1u;
+    while (frontier) {
+        uint32_t nb = 0;
+        for (uint32_t t = frontier; t; t &= t - 1) nb |= adj[__builtin_ctz(t)];
+        frontier = nb & full & ~seen;
+        seen |= frontier;
+    }
+    return seen == full ? MPDP_OK : MPDP_ENOTCONNECTED;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t mpdp_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries) {
+    BatchLayout B;
+    return batch_layout(nq, queries, B) ? B.total : 0;
+}
+
+mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                                uint32_t flags, mpdp_plan_node *plans_out, double *costs_out,
+                                double *latency_us_out, double *start_us_out, mpdp_batch_stats *stats_out) {
+    const double t0 = now_ms();
+    if (nq == 0 || !queries || !cardinalities || !plans_out || !costs_out) return MPDP_EINVAL;
+    if (cost_model != MPDP_COST_COUT && cost_model != MPDP_COST_PGLIKE) return MPDP_EINVAL;
+    uint64_t sum_m = 0;
+    for (uint32_t i = 0; i < nq; ++i) sum_m += queries[i].m;
+    if (sum_m > 0 && (!edges || !selectivities)) return MPDP_EINVAL;
+    for (uint32_t i = 0; i < nq; ++i) {
+        const mpdp_status st = validate_batch_query(queries[i], edges, cardinalities, selectivities);
+        if (st != MPDP_OK) return st;
+    }
+    BatchLayout B;
+    if (!batch_layout(nq, queries, B)) return MPDP_EINVAL;
+    if (!d_workspace) return MPDP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return MPDP_EINVAL;
+    if (ws_bytes < B.total) return MPDP_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    char *base = static_cast<char *>(d_workspace);
+
+    // one host image of everything the kernel reads, uploaded in one copy
+    std::vector<char> up(B.plans);
+    uint32_t *binom = reinterpret_cast<uint32_t *>(up.data() + B.binom);
+    for (uint32_t a = 0; a <= 32; ++a)
+        for (uint32_t b = 0; b <= 32; ++b) binom[a * 33 + b] = (uint32_t)binom64(a, b);
+    auto *bc = reinterpret_cast<mpdp::BatchCounters *>(up.data() + B.counters);
+    bc->next = 0;
+    bc->pad = 0;
+    bc->t0 = ~0ull;
+    auto *dq = reinterpret_cast<mpdp::BatchQueryDev *>(up.data() + B.queries);
+    uint32_t *de = reinterpret_cast<uint32_t *>(up.data() + B.edges);
+    double *dc = reinterpret_cast<double *>(up.data() + B.cards);
+    double *ds = reinterpret_cast<double *>(up.data() + B.sels);
+    // descriptors in the order the workgroups take them: larger queries first
+    std::vector<uint32_t> order(nq);
+    for (uint32_t i = 0; i < nq; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return queries[a].n > queries[b].n; });
+    std::vector<uint64_t> plan_at(nq);
+    {
+        uint64_t p = 0;
+        for (uint32_t i = 0; i < nq; ++i) { plan_at[i] = p; p += 2ull * queries[i].n - 1; }
+    }
+    uint64_t eo = 0, co = 0;
+    for (uint32_t j = 0; j < nq; ++j) {
+        const uint32_t i = order[j];
+        const mpdp_batch_query &Q = queries[i];
+        const uint64_t po = plan_at[i];
+        dq[j] = mpdp::BatchQueryDev{Q.n, Q.m, Q.m == Q.n - 1 ? 1u : 0u, (uint32_t)cost_model, co, eo, po};
+        for (uint32_t v = 0; v < Q.n; ++v) dc[co + v] = cardinalities[Q.card_offset + v];
+        for (uint32_t e = 0; e < Q.m; ++e) {
+            de[2 * (eo + e)] = edges[Q.edge_offset + e].u;
+            de[2 * (eo + e) + 1] = edges[Q.edge_offset + e].v;
+            ds[eo + e] = selectivities[Q.edge_offset + e];
+        }
+        co += Q.n;
+        eo += Q.m;
+    }
+    int dev = 0, rate_khz = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    const bool timing = (flags & MPDP_FLAG_TIMING) != 0;
+    EventPool ev;
+    if (timing) HIPCHK(ev.make(2));
+    HIPCHK(hipMemcpyAsync(base, up.data(), up.size(), hipMemcpyHostToDevice, s));
+    if (timing) HIPCHK(hipEventRecord(ev.ev[0], s));
+    HIPCHK(mpdp::launch_batch(cost_model, B.workgroups, reinterpret_cast<mpdp::BatchQueryDev *>(base + B.queries),
+                              nq, reinterpret_cast<uint32_t *>(base + B.edges),
+                              reinterpret_cast<double *>(base + B.cards), reinterpret_cast<double *>(base + B.sels),
+                              reinterpret_cast<uint32_t *>(base + B.binom), base + B.slots, B.slot_bytes, B.maxn,
+                              reinterpret_cast<mpdp_plan_node *>(base + B.plans),
+                              reinterpret_cast<mpdp::BatchOut *>(base + B.out),
+                              reinterpret_cast<mpdp::BatchCounters *>(base + B.counters), s));
+    if (timing) HIPCHK(hipEventRecord(ev.ev[1], s));
+    std::vector<mpdp::BatchOut> outs(nq);
+    mpdp::BatchCounters hbc{};
+    HIPCHK(hipMemcpyAsync(plans_out, base + B.plans, sizeof(mpdp_plan_node) * B.sum_nodes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(outs.data(), base + B.out, sizeof(mpdp::BatchOut) * nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hbc, base + B.counters, sizeof(hbc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    mpdp_batch_stats st{};
+    const double us_per_tick = rate_khz > 0 ? 1e3 / (double)rate_khz : 0.0;
+    for (uint32_t j = 0; j < nq; ++j) {
+        const mpdp::BatchOut &o = outs[j];
+        const uint32_t i = order[j];
+        if (o.error) return MPDP_EDEVICE;
+        costs_out[i] = o.cost;
+        if (latency_us_out) latency_us_out[i] = (double)(o.t_end - hbc.t0) * us_per_tick;
+        if (start_us_out) start_us_out[i] = (double)(o.t_start - hbc.t0) * us_per_tick;
+        st.connected_sets += o.connected;
+        st.ccp_pairs += o.ccp;
+        st.evaluated_pairs += o.evaluated;
+    }
+    if (stats_out) {
+        if (timing) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev.ev[0], ev.ev[1]));
+            st.ms_kernel = ms;
+        }
+        st.workgroups = B.workgroups;
+        st.max_n = B.maxn;
+        st.ms_total = now_ms() - t0;
+        *stats_out = st;
+    }
+    return MPDP_OK;
+}
+
 
 const char *mpdp_status_str(mpdp_status s) {
     switch (s) {

@@ -58,6 +58,32 @@ struct Counters {
     unsigned long long ccp;       // unordered csg-cmp pairs (general path)
 };
 
+// Batched path (mpdp_batch.hip): one query per workgroup at a time.
+struct BatchQueryDev {
+    uint32_t n, m, is_tree, cost_model;
+    uint64_t card_off, edge_off, plan_off;
+};
+
+struct BatchOut {
+    double cost;
+    unsigned long long t_start, t_end;  // device wall clock at the query's start and end
+    unsigned long long connected, ccp, evaluated;
+    uint32_t error, pad;
+};
+
+struct BatchCounters {
+    uint32_t next, pad;      // next query to take
+    unsigned long long t0;   // earliest workgroup start (device wall clock)
+};
+
+constexpr uint32_t kBatchMaxRel = 20;      // largest query the batched path takes
+constexpr uint32_t kBatchWorkgroups = 512; // persistent workgroups (two per CU)
+
+hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs, uint32_t nq,
+                        const uint32_t *edges, const double *cards, const double *sels, const uint32_t *binom,
+                        char *slots, uint64_t slot_bytes, uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
+                        BatchCounters *bc, hipStream_t s);
+
 hipError_t launch_init(const DevGraph *g, uint32_t n, MemoPtrs memo, Counters *cnt, hipStream_t s);
 hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t *list, Counters *cnt,
                          hipStream_t s);

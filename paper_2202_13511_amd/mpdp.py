@@ -24,7 +24,7 @@ MPDP_FLAG_TIMING = 1
 _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
-            "mpdp_optimize_ws"]
+            "mpdp_optimize_ws", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch"]
 
 
 class mpdp_edge(ctypes.Structure):
@@ -42,6 +42,17 @@ class mpdp_stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_filter", ctypes.c_double),
                 ("ms_eval", ctypes.c_double), ("levels", ctypes.c_uint32),
                 ("eval_launches", ctypes.c_uint32)]
+
+
+class mpdp_batch_query(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("card_offset", ctypes.c_uint32),
+                ("edge_offset", ctypes.c_uint32)]
+
+
+class mpdp_batch_stats(ctypes.Structure):
+    _fields_ = [("connected_sets", ctypes.c_uint64), ("evaluated_pairs", ctypes.c_uint64),
+                ("ccp_pairs", ctypes.c_uint64), ("ms_total", ctypes.c_double), ("ms_kernel", ctypes.c_double),
+                ("workgroups", ctypes.c_uint32), ("max_n", ctypes.c_uint32)]
 
 
 class MpdpError(RuntimeError):
@@ -75,6 +86,13 @@ def load(path: str = LIB_PATH):
     L.mpdp_optimize.restype = ctypes.c_int
     L.mpdp_optimize_ws.argtypes = common + [vp, sz, vp, u32] + outs
     L.mpdp_optimize_ws.restype = ctypes.c_int
+    bq = ctypes.POINTER(mpdp_batch_query)
+    L.mpdp_batch_workspace_bytes.argtypes = [u32, bq]
+    L.mpdp_batch_workspace_bytes.restype = sz
+    L.mpdp_optimize_batch.argtypes = [u32, bq, ctypes.POINTER(mpdp_edge), f64p, f64p, ctypes.c_int, vp, sz, vp,
+                                      u32, ctypes.POINTER(mpdp_plan_node), f64p, f64p, f64p,
+                                      ctypes.POINTER(mpdp_batch_stats)]
+    L.mpdp_optimize_batch.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -199,3 +217,69 @@ def memo_arrays(ws, n: int) -> dict:
         seg = ws[lay[name]: lay[name] + N * width].cpu().numpy().view(dt)
         out[name] = seg[idx]
     return out
+
+
+@dataclass
+class BatchResult:
+    costs: list           # root cost per query
+    plans: list           # per query: list of plan-node dicts (layout of mpdp_plan_node)
+    latency_us: np.ndarray
+    stats: dict
+    start_us: np.ndarray = None
+
+
+def _batch_marshal(queries):
+    qs = (mpdp_batch_query * len(queries))()
+    cards, edges, sels = [], [], []
+    co = eo = 0
+    for i, q in enumerate(queries):
+        qs[i] = mpdp_batch_query(q.n, q.m, co, eo)
+        cards.append(np.asarray(q.card, np.float64))
+        edges.append(np.asarray(q.edges, np.uint32).reshape(-1, 2))
+        sels.append(np.asarray(q.sel, np.float64))
+        co += q.n
+        eo += q.m
+    c = np.ascontiguousarray(np.concatenate(cards))
+    e = np.ascontiguousarray(np.concatenate(edges)) if eo else np.zeros((1, 2), np.uint32)
+    s = np.ascontiguousarray(np.concatenate(sels)) if eo else np.zeros(1, np.float64)
+    return qs, c, e, s
+
+
+def mpdp_batch_workspace_bytes(queries) -> int:
+    qs, _, _, _ = _batch_marshal(queries)
+    return int(load().mpdp_batch_workspace_bytes(len(queries), qs))
+
+
+def batch_workspace(queries, device="cuda"):
+    import torch
+    return torch.empty(max(mpdp_batch_workspace_bytes(queries), 256), dtype=torch.uint8, device=device)
+
+
+def mpdp_optimize_batch(queries, cost_model: int, ws, stream=None, flags: int = 0) -> BatchResult:
+    """All queries (n <= 20 each) in one persistent launch."""
+    import torch
+    qs, c, e, s = _batch_marshal(queries)
+    if stream is None:
+        stream = torch.cuda.current_stream(ws.device)
+    total = sum(2 * q.n - 1 for q in queries)
+    plans = (mpdp_plan_node * total)()
+    costs = np.zeros(len(queries), np.float64)
+    lat = np.zeros(len(queries), np.float64)
+    start = np.zeros(len(queries), np.float64)
+    st = mpdp_batch_stats()
+    f64p = ctypes.POINTER(ctypes.c_double)
+    rc = load().mpdp_optimize_batch(len(queries), qs, e.ctypes.data_as(ctypes.POINTER(mpdp_edge)),
+                                    c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), int(cost_model),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                    ctypes.c_void_p(stream.cuda_stream), int(flags), plans,
+                                    costs.ctypes.data_as(f64p), lat.ctypes.data_as(f64p),
+                                    start.ctypes.data_as(f64p), ctypes.byref(st))
+    if rc != MPDP_OK:
+        raise MpdpError(rc, mpdp_status_str(rc))
+    out, at = [], 0
+    for q in queries:
+        k = 2 * q.n - 1
+        out.append([dict(left=p.left, right=p.right, relset=p.relset, op=p.op, cost=p.cost, card=p.card)
+                    for p in plans[at: at + k]])
+        at += k
+    return BatchResult(costs.tolist(), out, lat, {f: getattr(st, f) for f, _ in mpdp_batch_stats._fields_}, start)

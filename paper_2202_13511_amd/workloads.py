@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "Query", "star", "snowflake", "chain", "cycle", "cycle_chords", "clique",
-    "random_connected", "random_tree", "from_edges", "all_equal_clique",
+    "random_connected", "random_tree", "from_edges", "all_equal_clique", "batch_mixed",
 ]
 
 
@@ -186,3 +186,38 @@ def random_connected(n: int, seed: int, extra: float = 0.3) -> Query:
     e = np.array(sorted(es), dtype=np.uint32).reshape(-1, 2)
     card, sel = _stats(rng, n, e)
     return Query(n, e, card, sel, f"rconn{n}-p{extra}-s{seed}")
+
+
+def batch_mixed(count: int, seed: int, n_range=(8, 20)) -> list[Query]:
+    """Mixed batch: n ~ U{n_range}, topology uniform over chain, star, cycle
+    (ring plus U{0..2} chords), snowflake (depth 3, fanout U{2..4}) and
+    random (spanning tree plus U{1..3} extra edges); statistics as above.
+    Query i uses the sub-seed (seed, i)."""
+    kinds = ("chain", "star", "cycle", "snowflake", "random")
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64([seed, i]))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        kind = kinds[int(rng.integers(0, len(kinds)))]
+        s = int(rng.integers(0, 2 ** 31))
+        if kind == "chain":
+            q = chain(n, s)
+        elif kind == "star":
+            q = star(n, s)
+        elif kind == "cycle" and n >= 3:
+            q = cycle_chords(s, n=n, chords=int(rng.integers(0, 3)))
+        elif kind == "cycle":
+            q = chain(n, s)
+        elif kind == "snowflake":
+            q = snowflake(n, s)
+        else:
+            q = random_tree(n, s)
+            extra = int(rng.integers(1, 4))
+            have = {tuple(sorted(e)) for e in q.edges.tolist()}
+            cand = [(a, b) for a in range(n) for b in range(a + 1, n) if (a, b) not in have]
+            pick = rng.choice(len(cand), size=min(extra, len(cand)), replace=False)
+            es = sorted(have) + sorted(cand[int(p)] for p in pick)
+            q = from_edges(n, es, s, f"random{n}+{extra}-s{s}")
+        q.name = f"batch{seed}/{i}:{q.name}"
+        out.append(q)
+    return out

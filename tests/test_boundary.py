@@ -101,3 +101,29 @@ def test_single_relation_needs_no_device():
     assert r.plan == [dict(left=-1, right=-1, relset=1, op=mpdp.MPDP_OP_SCAN, cost=0.01 * 1234.0, card=1234.0)]
     r = mpdp.mpdp_optimize(q, mpdp.MPDP_COST_COUT)
     assert r.cost == 0.0
+
+
+def test_batch_validation_without_gpu():
+    lib = mpdp.load()
+    good = [W.chain(5, 0), W.star(6, 1)]
+    assert mpdp.mpdp_batch_workspace_bytes(good) > 0
+    assert mpdp.mpdp_batch_workspace_bytes(good + [W.chain(21, 2)]) == 0  # n > 20
+    import torch  # noqa: F401  (tensor-free calls below never touch a device)
+
+    def status(queries):
+        qs, c, e, s = mpdp._batch_marshal(queries)
+        plans = (mpdp.mpdp_plan_node * sum(2 * q.n - 1 for q in queries))()
+        costs = np.zeros(len(queries))
+        f64p = ctypes.POINTER(ctypes.c_double)
+        return lib.mpdp_optimize_batch(len(queries), qs, e.ctypes.data_as(ctypes.POINTER(mpdp.mpdp_edge)),
+                                       c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), 0, None, 0, None, 0, plans,
+                                       costs.ctypes.data_as(f64p), None, None, None)
+
+    assert status(good + [W.chain(21, 2)]) == mpdp.MPDP_ETOOLARGE
+    bad = W.chain(5, 3)
+    bad.edges = bad.edges.copy()
+    bad.edges[1] = [2, 2]
+    assert status(good + [bad]) == mpdp.MPDP_EINVAL
+    disc = W.Query(4, np.array([[0, 1], [2, 3]], np.uint32), np.full(4, 10.0), np.full(2, 0.5))
+    assert status([disc]) == mpdp.MPDP_ENOTCONNECTED
+    assert status(good) == mpdp.MPDP_EINVAL  # valid queries, but no workspace

@@ -1,0 +1,52 @@
+"""GPU parity of the batched entry point (many small queries, one launch)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_13511_amd import mpdp, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def check_against_oracle(queries, res, cm):
+    for q, cost, plan in zip(queries, res.costs, res.plans):
+        ref = oracle.mpdp(q, cm)
+        assert np.float64(cost).view(np.uint64) == np.float64(ref.root_cost).view(np.uint64), q.name
+        want = oracle.plan_from_memo(ref)
+        got = [(p["relset"], p["left"], p["right"], p["op"]) for p in plan]
+        assert got == [(p["relset"], p["left"], p["right"], p["op"]) for p in want], q.name
+        for a, b in zip(plan, want):
+            assert np.float64(a["cost"]).view(np.uint64) == np.float64(b["cost"]).view(np.uint64)
+            assert np.float64(a["card"]).view(np.uint64) == np.float64(b["card"]).view(np.uint64)
+
+
+@pytest.mark.parametrize("cm", [mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE])
+def test_batch_parity_small(cm):
+    queries = W.batch_mixed(96, 7, n_range=(1, 13)) + [W.clique(9, 1), W.all_equal_clique(8)]
+    ws = mpdp.batch_workspace(queries)
+    res = mpdp.mpdp_optimize_batch(queries, cm, ws)
+    check_against_oracle(queries, res, cm)
+    conn = sum(oracle.mpdp(q, cm).connected_sets for q in queries)
+    ccp = sum(oracle.mpdp(q, cm).ccp_ordered // 2 for q in queries)
+    assert res.stats["connected_sets"] == conn and res.stats["ccp_pairs"] == ccp
+    assert np.all(res.latency_us > 0)
+
+
+def test_batch_more_queries_than_workgroups():
+    """More queries than persistent workgroups: slots are reused."""
+    queries = W.batch_mixed(1100, 3, n_range=(4, 9))
+    ws = mpdp.batch_workspace(queries)
+    res = mpdp.mpdp_optimize_batch(queries, mpdp.MPDP_COST_COUT, ws)
+    check_against_oracle(queries[::7], type(res)(res.costs[::7], res.plans[::7], res.latency_us[::7], res.stats),
+                         mpdp.MPDP_COST_COUT)
+    assert np.all(res.start_us <= res.latency_us)
+    assert res.stats["workgroups"] == 512
+
+
+def test_batch_equals_single_calls():
+    queries = W.batch_mixed(40, 11, n_range=(14, 20))
+    ws = mpdp.batch_workspace(queries)
+    res = mpdp.mpdp_optimize_batch(queries, mpdp.MPDP_COST_PGLIKE, ws)
+    for q, cost, plan in zip(queries, res.costs, res.plans):
+        one = mpdp.mpdp_optimize(q, mpdp.MPDP_COST_PGLIKE)
+        assert cost == one.cost and plan == one.plan, q.name
