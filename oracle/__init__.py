@@ -66,6 +66,8 @@ def lib():
         L.oracle_dpsub.restype = i
         L.oracle_mpdp.argtypes = memo_sig + [i] + out_sig
         L.oracle_mpdp.restype = i
+        L.oracle_mpdp_bc.argtypes = memo_sig + [f64p] + out_sig
+        L.oracle_mpdp_bc.restype = i
         L.oracle_dpccp.argtypes = memo_sig + out_sig
         L.oracle_dpccp.restype = i
         L.oracle_count_ccp.argtypes = [i, i, u32p]
@@ -144,7 +146,15 @@ def dpsub(q, cost_model=COST_COUT) -> Memo:
 
 
 def mpdp(q, cost_model=COST_COUT, force_general=False) -> Memo:
-    """MPDP: Alg. 2 when the join graph is a tree, else Alg. 3 (n <= 30)."""
+    """MPDP: Alg. 2 when the join graph is a tree, else Alg. 3 (n <= 30).
+    A query with ``base_cost`` set treats relation v as an intermediate
+    result whose plan costs base_cost[v]."""
+    bc = getattr(q, "base_cost", None)
+    if bc is not None:
+        if force_general:
+            raise ValueError("force_general is not combined with base costs")
+        b = np.ascontiguousarray(bc, dtype=np.float64)
+        return _run(lib().oracle_mpdp_bc, q, cost_model, _p(b, ctypes.c_double))
     return _run(lib().oracle_mpdp, q, cost_model, int(bool(force_general)))
 
 

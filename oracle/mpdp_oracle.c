@@ -63,6 +63,8 @@ typedef struct {
     uint32_t adj[32];
     double card[32];
     double sel[32][32];
+    int has_bcost;      /* relations are intermediate results with given plan costs */
+    double bcost[32];
 } og;
 
 typedef struct {
@@ -146,8 +148,12 @@ static double card_of(const og *g, uint32_t S)
     return (c < 1.0) ? 1.0 : c;
 }
 
+/* Cost of the plan of a single relation: a scan (0 under C_out, one tuple
+ * cost per row under the PostgreSQL-like model), or, for a relation that
+ * stands for an already planned intermediate result, that plan's cost. */
 static double base_cost(const og *g, int v)
 {
+    if (g->has_bcost) return g->bcost[v];
     return g->cost_model == CM_PGLIKE ? 0.01 * g->card[v] : 0.0;
 }
 
@@ -323,12 +329,37 @@ static int graph_is_tree(const og *g, int m)
     return m == g->n - 1 && connected(g, all);
 }
 
+static int mpdp_run(og *gp, int m, int force_general, double *mcost, double *mcard, uint32_t *mleft,
+                    uint8_t *mop, uint64_t *counters);
+
 int oracle_mpdp(int n, int m, const uint32_t *edges, const double *card, const double *sel,
                 int cost_model, int force_general, double *mcost, double *mcard, uint32_t *mleft,
                 uint8_t *mop, uint64_t *counters)
 {
     og g;
     if (n > 30 || og_build(&g, n, m, edges, card, sel, cost_model)) return -1;
+    return mpdp_run(&g, m, force_general, mcost, mcard, mleft, mop, counters);
+}
+
+/* MPDP where every relation carries the cost of its plan (bcost[v]): the
+ * exact step of the large-query heuristics, whose relations may be
+ * intermediate results planned earlier. */
+int oracle_mpdp_bc(int n, int m, const uint32_t *edges, const double *card, const double *sel,
+                   int cost_model, const double *bcost, double *mcost, double *mcard, uint32_t *mleft,
+                   uint8_t *mop, uint64_t *counters)
+{
+    og g;
+    if (n > 30 || og_build(&g, n, m, edges, card, sel, cost_model)) return -1;
+    g.has_bcost = 1;
+    for (int v = 0; v < n; v++) g.bcost[v] = bcost[v];
+    return mpdp_run(&g, m, 0, mcost, mcard, mleft, mop, counters);
+}
+
+static int mpdp_run(og *gp, int m, int force_general, double *mcost, double *mcard, uint32_t *mleft,
+                    uint8_t *mop, uint64_t *counters)
+{
+    og g = *gp;
+    int n = g.n;
     omemo M = {mcost, mcard, mleft, mop};
     ocount C = {0, 0, 0};
     memo_init(&g, &M);

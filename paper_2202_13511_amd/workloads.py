@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "Query", "star", "snowflake", "chain", "cycle", "cycle_chords", "clique",
-    "random_connected", "random_tree", "from_edges", "all_equal_clique", "batch_mixed",
+    "random_connected", "random_tree", "from_edges", "all_equal_clique", "batch_mixed", "large_snowflake",
 ]
 
 
@@ -36,6 +36,8 @@ class Query:
     card   (n,) float64 base-relation cardinalities (finite, >= 1)
     sel    (m,) float64 selectivity of each edge, in (0, 1]
     name   free-form label of the workload and seed
+    base_cost  optional (n,) float64: relation v is an intermediate result
+           whose plan costs base_cost[v] (None: every relation is a scan)
     """
     n: int
     edges: np.ndarray
@@ -43,6 +45,7 @@ class Query:
     sel: np.ndarray
     name: str = ""
     meta: dict = field(default_factory=dict)
+    base_cost: np.ndarray | None = None
 
     @property
     def m(self) -> int:
@@ -221,3 +224,38 @@ def batch_mixed(count: int, seed: int, n_range=(8, 20)) -> list[Query]:
         q.name = f"batch{seed}/{i}:{q.name}"
         out.append(q)
     return out
+
+
+def large_snowflake(n: int, seed: int, cross: int | None = None) -> Query:
+    """Large snowflake with random cross edges (100-1000 relations): root 0,
+    breadth-first labelling, every node above depth 4 draws U{2..F} children
+    with F = max(4, ceil(2 n^(1/4))), truncated at n nodes (a tree that ends
+    short is redrawn from the same generator); then ``cross`` (default
+    round(n / 20)) distinct extra edges drawn uniformly among the non-edges."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    F = max(4, int(np.ceil(2.0 * n ** 0.25)))
+    while True:
+        parent, lvl, head = [-1], [0], 0
+        while head < len(parent) and len(parent) < n:
+            if lvl[head] < 4:
+                for _ in range(int(rng.integers(2, F + 1))):
+                    if len(parent) >= n:
+                        break
+                    parent.append(head)
+                    lvl.append(lvl[head] + 1)
+            head += 1
+        if len(parent) == n:
+            break
+    es = {(parent[c], c) for c in range(1, n)}
+    extra = int(round(n / 20)) if cross is None else int(cross)
+    added = 0
+    while added < extra:
+        a, b = (int(x) for x in rng.integers(0, n, size=2))
+        e = (min(a, b), max(a, b))
+        if a == b or e in es:
+            continue
+        es.add(e)
+        added += 1
+    e = np.array(sorted(es), dtype=np.uint32).reshape(-1, 2)
+    card, sel = _stats(rng, n, e)
+    return Query(n, e, card, sel, f"lsnow{n}+{extra}-s{seed}", {"depth": max(lvl)})
