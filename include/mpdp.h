@@ -150,6 +150,21 @@ mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges,
                              double *cost_out, mpdp_stats *stats_out);
 
 /*
+ * As mpdp_optimize_ws for a query whose relations stand for intermediate
+ * results that are already planned (the exact step of IDP2 and UnionDP,
+ * Section 4: "temporary tables" and composite nodes): relation v costs
+ * base_costs[v] (host, n values, finite, >= 0) instead of its scan; its
+ * cardinality is cardinalities[v] as usual.  Everything else, including the
+ * workspace size, is as in mpdp_optimize_ws.  MPDP_EINVAL if base_costs is
+ * NULL or holds a negative or non-finite value.
+ */
+mpdp_status mpdp_optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                const double *base_costs, mpdp_cost_model cost_model,
+                                void *d_workspace, size_t ws_bytes, void *hip_stream, uint32_t flags,
+                                mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out);
+
+/*
  * Batched optimization: many small queries in one launch.
  *
  * Query q has n relations whose cardinalities are
@@ -200,6 +215,74 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
                                 void *hip_stream, uint32_t flags, mpdp_plan_node *plans_out,
                                 double *costs_out, double *latency_us_out, double *start_us_out,
                                 mpdp_batch_stats *stats_out);
+
+/*
+ * Large queries (Section 4): heuristics that hand sub-problems of at most k
+ * units to the exact DP above, on the GPU.
+ *   MPDP_LARGE_GOO      greedy operator ordering alone: join the two
+ *                       connected trees whose union has the smallest card
+ *   MPDP_LARGE_IDP2     IDP2 (Section 4.1) with GOO's plan as the start:
+ *                       repeatedly re-plan, exactly, the costliest subtree of
+ *                       2..k units and make it one unit
+ *   MPDP_LARGE_UNIONDP  UnionDP (Section 4.2, Alg. 4): partition the graph of
+ *                       units into connected parts of at most k units (union
+ *                       order: size of the two parts, then the card of the
+ *                       edge's two units), plan each part exactly (all parts
+ *                       of one round in one batched launch when they have at
+ *                       most 20 units), and repeat on the graph of parts
+ * A unit reaches the exact step as one relation: card(S) of its relation
+ * set, its plan's cost as base cost, and one edge to each adjacent unit
+ * whose selectivity is the product of the base selectivities between them
+ * (edge-list order; clamped below at the smallest normal double).  Every
+ * plan is finally re-costed over the base relations: card(S) as defined at
+ * the top of this header for any relation set, each join in its cheaper
+ * orientation and operator (key: cost, then the left relation set read as a
+ * binary number, then HASH before NESTLOOP).  cost_out is that cost.
+ */
+typedef enum { MPDP_LARGE_GOO = 0, MPDP_LARGE_IDP2 = 1, MPDP_LARGE_UNIONDP = 2 } mpdp_large_method;
+
+/* Plan node of a large query.  Nodes 0..n-1 are the relations in index
+ * order; join nodes follow in post-order (left child first); the root is
+ * node 2n-2. */
+typedef struct {
+    int32_t left, right;  /* child node indices, -1 for leaves                 */
+    uint32_t rel;         /* leaf: its relation; join: lowest relation below it */
+    uint32_t nrels;       /* relations below this node                        */
+    uint32_t op, pad;     /* mpdp_op                                          */
+    double cost, card;
+} mpdp_large_node;
+
+typedef struct {
+    uint64_t exact_calls;  /* sub-problems planned by the exact DP              */
+    uint64_t exact_units;  /* units over all exact sub-problems                 */
+    uint32_t max_units;    /* largest exact sub-problem                         */
+    uint32_t rounds;       /* IDP2 iterations or UnionDP partition rounds       */
+    uint32_t launches;     /* exact-step calls into the GPU (a batch counts 1)  */
+    uint32_t pad;
+    double ms_total;       /* host wall time of the call                        */
+    double ms_exact;       /* of which in the exact step (upload, kernels, readback) */
+} mpdp_large_stats;
+
+/*
+ * Plan a query of 1 <= n <= 4096 relations with `method` and sub-problem
+ * bound 2 <= k <= 25 (ignored by GOO).  Inputs follow mpdp_optimize (edges
+ * with distinct unordered endpoint pairs, card >= 1 finite, sel in (0, 1],
+ * connected join graph), except for the bound on n.
+ *   plan_out   host, caller-allocated, 2n-1 nodes (layout above)
+ *   cost_out   host, the plan's re-costed cost
+ *   stats_out  host, optional
+ * The library allocates its device workspace (for k units, or for a round of
+ * batched parts) and frees it before returning; it runs on hip_stream (NULL:
+ * the null stream).  MPDP_EINVAL for malformed input, k out of range or an
+ * unknown method; MPDP_ENOTCONNECTED; MPDP_ETOOLARGE for n > 4096;
+ * MPDP_ENOMEM / MPDP_EDEVICE from the device.  Outputs are written only on
+ * MPDP_OK.
+ */
+mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
+                                void *hip_stream, mpdp_large_node *plan_out, double *cost_out,
+                                mpdp_large_stats *stats_out);
 
 #ifdef __cplusplus
 }

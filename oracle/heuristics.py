@@ -42,6 +42,7 @@ H6  UnionDP: the size of a partition counts units; the weight of an edge
 from __future__ import annotations
 
 import heapq
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -51,6 +52,9 @@ import oracle
 COUT, PGLIKE = oracle.COST_COUT, oracle.COST_PGLIKE
 OP_SCAN, OP_HASH, OP_NESTLOOP, OP_JOIN = oracle.OP_SCAN, oracle.OP_HASH, oracle.OP_NESTLOOP, 3
 DBL_MIN = float(np.finfo(np.float64).tiny)
+
+# plans are walked recursively; a plan is at most n joins deep
+sys.setrecursionlimit(max(sys.getrecursionlimit(), 20000))
 
 
 class Graph:

@@ -23,7 +23,7 @@ constexpr int kBW = kBatchBlock / 64;
 // Build the LDS image of one query inside the workgroup (everything except
 // the binomials, which are staged once per workgroup).
 __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t *edges, const double *cards,
-                            const double *sels) {
+                            const double *sels, const double *bcosts) {
     const uint32_t t = threadIdx.x, n = Q.n, m = Q.m;
     const uint32_t *E = edges + 2ull * Q.edge_off;
     const double *C = cards + Q.card_off;
@@ -33,7 +33,9 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
         L.pbit[t] = 0;
         L.desc[t] = 1u << t;
         L.card[t] = t < n ? C[t] : 1.0;
-        L.bcost[t] = t < n ? (Q.cost_model == MPDP_COST_PGLIKE ? 0.01 * C[t] : 0.0) : 0.0;
+        if (t >= n) L.bcost[t] = 0.0;
+        else if (bcosts) L.bcost[t] = bcosts[Q.card_off + t];  // planned intermediate results
+        else L.bcost[t] = Q.cost_model == MPDP_COST_PGLIKE ? 0.01 * C[t] : 0.0;
     }
     __syncthreads();
     for (uint32_t e = t; e < m; e += blockDim.x) {
@@ -88,9 +90,9 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
 }
 
 template <int CM>
-__global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, uint32_t nq, const uint32_t *edges,
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_batch(const BatchQueryDev *qs, uint32_t nq, const uint32_t *edges,
                                                        const double *cards, const double *sels,
-                                                       const uint32_t *binom_g, char *slots, uint64_t slot_bytes,
+                                                       const double *bcosts, const uint32_t *binom_g, char *slots, uint64_t slot_bytes,
                                                        uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
                                                        BatchCounters *bc) {
     __shared__ __align__(16) LdsGraph L;
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, 
     __shared__ SetBlocks hsb;
     __shared__ Key hkeys[kBW];
     __shared__ PlanScratch P;
-    __shared__ uint32_t s_q, s_count, s_hcount, s_level;
+    __shared__ uint32_t s_q, s_ntree, s_ngen, s_hcount, s_level;
     __shared__ unsigned long long s_conn, s_ccp, s_eval, s_t0;
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     if (t == 0) atomicMin(&bc->t0, (unsigned long long)wall_clock64());
@@ -112,8 +114,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, 
                reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
     const uint64_t list_off = (21 * N + 255) & ~255ull;
     uint32_t *list = reinterpret_cast<uint32_t *>(slot + list_off);
-    uint32_t *heavy = list + L.binom[maxn * 33 + maxn / 2];
-    (void)heavy;
+    const uint32_t cap = L.binom[maxn * 33 + maxn / 2];  // sets of the widest level
+    uint32_t *hv = list + cap;
 
     for (;;) {
         if (t == 0) s_q = atomicAdd(&bc->next, 1u);
@@ -121,9 +123,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, 
         const uint32_t q = s_q;
         if (q >= nq) break;
         const BatchQueryDev Q = qs[q];
-        build_image(L, Q, edges, cards, sels);
+        build_image(L, Q, edges, cards, sels, bcosts);
         const uint32_t n = Q.n;
-        uint32_t *hv = list + L.binom[maxn * 33 + maxn / 2];
         if (t == 0) {
             s_t0 = (unsigned long long)wall_clock64();
             s_conn = 0;
@@ -156,43 +157,28 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, 
                 __syncthreads();
                 continue;
             }
-            if (t == 0) { s_count = 0; s_hcount = 0; }
+            if (t == 0) { s_ntree = 0; s_ngen = 0; s_hcount = 0; }
             __syncthreads();
-            filter_wave(L, (int)n, k, ncand, wave, kBW, list, &s_count, lane);
+            filter_wave(L, (int)n, k, ncand, wave, kBW, list, cap, &s_ntree, &s_ngen, lane);
             __syncthreads();
-            const uint32_t count = s_count;
-            // light sets: one wave each
-            for (uint32_t idx = wave; idx < count; idx += kBW) {
-                const uint32_t S = list[idx];
-                const SetBlocks sb = analyze_set(L, S, WS[wave], lane);
-                if (sb.total_chunks > kHeavyChunks) {
-                    if (lane == 0) hv[atomicAdd(&s_hcount, 1u)] = S;
-                    wave_sync_lds();
-                    continue;
-                }
-                if (lane == 0) my_eval += sb.evaluated;
-                wave_sync_lds();
-                const double cardS = card_of(L, S);
-                Key best = worst_key();
-                eval_chunks<CM>(L, M, WS[wave], S, sb.A, sb.total_chunks, lane, 64u, cardS, best, my_ccp);
-                best = wave_min(best);
-                if (lane == 0) store_best(M, memo_index(L, S), best, cardS);
-                wave_sync_lds();
-            }
+            const uint32_t count = s_ntree + s_ngen;
+            // light work: tree-inducing sets one per lane, other sets one per wave
+            light_sets<CM>(L, M, list, cap, s_ntree, s_ngen, wave, kBW, WS[wave], hv, &s_hcount, lane, my_ccp,
+                           my_eval);
             __syncthreads();
             // heavy sets: the whole workgroup each
             const uint32_t hcount = s_hcount;
             for (uint32_t h = 0; h < hcount; ++h) {
                 const uint32_t S = hv[h];
                 if (wave == 0) {
-                    const SetBlocks sb = analyze_set(L, S, WS[0], lane);
+                    const SetBlocks sb = analyze_set(L, S, WS[0], lane, blockDim.x);
                     if (lane == 0) { hsb = sb; my_eval += sb.evaluated; }
                 }
                 __syncthreads();
                 const SetBlocks sb = hsb;
-                const double cardS = card_of(L, S);
+                const double cardS = card_of_wave(L, S, threadIdx.x & 63u);
                 Key best = worst_key();
-                eval_chunks<CM>(L, M, WS[0], S, sb.A, sb.total_chunks, t, blockDim.x, cardS, best, my_ccp);
+                eval_chunks<CM>(L, M, WS[0], S, sb, t, blockDim.x, cardS, best, my_ccp);
                 best = wave_min(best);
                 if (lane == 0) hkeys[wave] = best;
                 __syncthreads();
@@ -239,15 +225,16 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const BatchQueryDev *qs, 
 }  // namespace
 
 hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs, uint32_t nq,
-                        const uint32_t *edges, const double *cards, const double *sels, const uint32_t *binom,
+                        const uint32_t *edges, const double *cards, const double *sels, const double *bcosts,
+                        const uint32_t *binom,
                         char *slots, uint64_t slot_bytes, uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
                         BatchCounters *bc, hipStream_t s) {
     if (cost_model == MPDP_COST_COUT)
         hipLaunchKernelGGL(k_batch<MPDP_COST_COUT>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, nq, edges, cards,
-                           sels, binom, slots, slot_bytes, maxn, plans, out, bc);
+                           sels, bcosts, binom, slots, slot_bytes, maxn, plans, out, bc);
     else
         hipLaunchKernelGGL(k_batch<MPDP_COST_PGLIKE>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, nq, edges,
-                           cards, sels, binom, slots, slot_bytes, maxn, plans, out, bc);
+                           cards, sels, bcosts, binom, slots, slot_bytes, maxn, plans, out, bc);
     return hipGetLastError();
 }
 

@@ -18,8 +18,7 @@ constexpr int kFilterChunk = 16;    // consecutive ranks per lane in k_filter (<
 constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tree (1, 2 or 4)
 constexpr int kRing = 384;          // per-wave ring of connected sets (>= 63 + 64 * kTreeChunkMax)
 constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
-constexpr int kEvalChunk = 16;      // block-local candidates per lane chunk
-constexpr uint32_t kHeavyChunks = 256;   // above this many chunks a set goes to k_eval_heavy
+constexpr uint32_t kHeavyChunks = 256;   // above this many 16-candidate chunks a set is heavy
 constexpr int kHeavyBlock = 1024;        // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
 
@@ -266,16 +265,94 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
 }
 
 
-// Key reduction across the 64 lanes of a wave.
+// Key reduction across the 64 lanes of a wave, returned to every lane:
+// four DPP row shifts leave each row's minimum in its last lane, and the
+// four row minima are combined from scalar copies.
+template <int kCtrl>
+__device__ __forceinline__ Key dpp_row_shr(const Key &b) {
+    // a lane whose source is outside its row keeps its own key
+    const uint32_t lo = (uint32_t)b.c, hi = (uint32_t)(b.c >> 32);
+    Key o;
+    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, kCtrl, 0xf, 0xf, false);
+    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, kCtrl, 0xf, 0xf, false);
+    o.c = ((unsigned long long)ohi << 32) | olo;
+    o.l = (uint32_t)__builtin_amdgcn_update_dpp((int)b.l, (int)b.l, kCtrl, 0xf, 0xf, false);
+    o.op = (uint32_t)__builtin_amdgcn_update_dpp((int)b.op, (int)b.op, kCtrl, 0xf, 0xf, false);
+    return o;
+}
+
+__device__ __forceinline__ Key key_at(const Key &b, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b.c, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b.c >> 32), lane);
+    return Key{((unsigned long long)hi << 32) | lo, (uint32_t)__builtin_amdgcn_readlane((int)b.l, lane),
+               (uint32_t)__builtin_amdgcn_readlane((int)b.op, lane)};
+}
+
 __device__ __forceinline__ Key wave_min(Key b) {
-    for (int off = 32; off >= 1; off >>= 1) {
-        Key o;
-        o.c = (unsigned long long)__shfl_xor((long long)b.c, off);
-        o.l = (uint32_t)__shfl_xor((int)b.l, off);
-        o.op = (uint32_t)__shfl_xor((int)b.op, off);
-        if (key_less(o, b)) b = o;
+    Key o = dpp_row_shr<0x111>(b);  // row_shr:1
+    if (key_less(o, b)) b = o;
+    o = dpp_row_shr<0x112>(b);      // row_shr:2
+    if (key_less(o, b)) b = o;
+    o = dpp_row_shr<0x114>(b);      // row_shr:4
+    if (key_less(o, b)) b = o;
+    o = dpp_row_shr<0x118>(b);      // row_shr:8
+    if (key_less(o, b)) b = o;
+    Key r = key_at(b, 15);
+    const Key r1 = key_at(b, 31), r2 = key_at(b, 47), r3 = key_at(b, 63);
+    if (key_less(r1, r)) r = r1;
+    if (key_less(r2, r)) r = r2;
+    if (key_less(r3, r)) r = r3;
+    return r;
+}
+
+// Sum over the lanes 0..31 of a wave of 32-bit values (DPP row scans, then
+// the two row totals), returned to every lane.
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 15) + (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+}
+
+// memo_index of a set S held by the whole wave: lane v adds the term of
+// relation v.
+__device__ __forceinline__ uint64_t memo_index_wave(const LdsGraph &L, uint32_t S, uint32_t lane) {
+    uint32_t term = 0;
+    if (lane < 32 && ((S >> lane) & 1u)) term = L.binom[lane * 33 + popc32(S & ((1u << lane) - 1u)) + 1];
+    return L.loff[popc32(S)] + wave_sum32(term);
+}
+
+__device__ __forceinline__ double rdlane_f64(double x, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// card(S) for a set S held by the whole wave, the same product in the same
+// order as card_of: the factors are loaded by all lanes at once (lane v:
+// card[v], adjacency and selectivity row of v; lane j and j + 64: the
+// selectivities j and j + 64 in edge order) and multiplied from scalar
+// copies.
+__device__ __forceinline__ double card_of_wave(const LdsGraph &L, uint32_t S, uint32_t lane) {
+    const uint32_t v_l = lane & 31u;
+    const double cv = L.card[v_l];
+    const uint32_t adjv = L.adj[v_l], rowv = L.selrow[v_l];
+    const double s0 = L.sel[lane], s1 = L.sel[lane + 64];
+    double c = 1.0;
+    for (uint32_t T = S; T; T &= T - 1) {
+        const int v = ctz32(T);
+        c = c * rdlane_f64(cv, v);
+        const uint32_t lower = (uint32_t)__builtin_amdgcn_readlane((int)adjv, v) & ((1u << v) - 1u);
+        const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)rowv, v);
+        for (uint32_t U = lower & S; U; U &= U - 1) {
+            const uint32_t j = row + (uint32_t)popc32(lower & (lowbit(U) - 1u));
+            const double x = j < 64u ? rdlane_f64(s0, (int)j) : j < 128u ? rdlane_f64(s1, (int)(j - 64u)) : L.sel[j];
+            c = c * x;
+        }
     }
-    return b;
+    return c < 1.0 ? 1.0 : c;
 }
 
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int lane) {
@@ -290,98 +367,108 @@ struct WaveScratch {
 
 struct SetBlocks {
     uint32_t A;             // cut vertices of G[S]
-    uint32_t total_chunks;  // candidate chunks over all blocks
+    uint32_t total_chunks;  // candidate chunks over all blocks, 2^shift candidates each
+    uint32_t shift;
+    uint32_t chunks16;      // chunks at 16 candidates each (decides light or heavy)
     unsigned long long evaluated;  // Alg. 3 candidates of S: sum over blocks of 2^b - 2
 };
 
 // Blocks of G[S] for one connected S, computed by one wave:
-//  1. cut vertices: lane v checks whether G[S - v] is connected;
-//  2. split S at a cut vertex into pieces {x} + component, and split pieces
-//     again until a piece has no cut vertex of its own.  A piece is a union
-//     of blocks of S; its attachment set holds the split vertices it still
-//     contains, which are not cut vertices of the piece, while every other
-//     cut vertex of S inside the piece is.  Control flow is uniform; the
-//     piece stack lives one entry per lane.
+//  1. a depth-first search from the lowest relation, uniform across the wave:
+//     the adjacency of the current relation comes from its lane by readlane,
+//     lane v records its parent and, on the way back, its subtree D(v);
+//  2. non-tree edges of a depth-first tree join a relation to an ancestor,
+//     so the parent p of v separates D(v) from the rest of S exactly when
+//     every neighbour of D(v) outside it is p (the lowpoint test); such a v
+//     is the top of one block;
+//  3. the block of top v is p plus D(v) without the subtrees of the tops
+//     below v; the cut vertices are the parents of tops, the root only when
+//     it has two or more children.
 // The block list, completeness flags and candidate-chunk prefix go to W.
-__device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, int lane) {
-    // degrees in G[S]; a connected S with |S| - 1 edges induces a tree, whose
-    // blocks are its edges and whose cut vertices are its inner relations
+// The half of a block's candidates that hold its lowest relation is cut into
+// chunks of 2^shift, with the smallest shift (up to 4) that leaves at most
+// `budget` chunks, so that the candidates of a small set still spread over
+// all the lanes that take part.
+__device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, int lane, uint32_t budget) {
     const bool mine = lane < 32 && ((S >> lane) & 1u);
-    const uint32_t deg = mine ? (uint32_t)popc32(L.adj[lane] & S) : 0u;
-    uint32_t edges2 = deg;
-    for (int off = 32; off >= 1; off >>= 1) edges2 += (uint32_t)__shfl_xor((int)edges2, off);
-    const int kS = popc32(S);
-    if (edges2 == 2u * (uint32_t)(kS - 1)) {
-        const uint32_t A = (uint32_t)__ballot(mine && deg >= 2);
-        // lane v owns the edges to its smaller neighbours in S
-        const uint32_t lower = mine ? (L.adj[lane] & S & ((1u << lane) - 1u)) : 0u;
-        const uint32_t cnt = (uint32_t)popc32(lower);
-        uint32_t before = 0;
-        for (int b = 0; b < 5; ++b)
-            before += (uint32_t)__popcll(__ballot((cnt >> b) & 1u) & ((1ull << lane) - 1ull)) << b;
-        uint32_t at = before;
-        for (uint32_t U = lower; U; U &= U - 1, ++at) {
-            W.blk[at] = lowbit(U) | (1u << lane);
-            W.full[at] = 1;
-            W.cpre[at] = at;
-        }
-        if (lane == 0) W.cpre[kS - 1] = (uint32_t)(kS - 1);
-        return SetBlocks{A, (uint32_t)(kS - 1), 2ull * (unsigned long long)(kS - 1)};
-    }
+    const uint32_t adjS = mine ? (L.adj[lane] & S) : 0u;
 
-    bool cut = false;
-    if (mine) {
-        const uint32_t R = S & ~(1u << lane);
-        cut = grow(L.nb, lowbit(R), R) != R;
-    }
-    const uint32_t A = (uint32_t)__ballot(cut);
-
-    uint32_t stkP = 0, stkA = 0, myblk = 0;
-    int sp = 0, nblk = 0, steps = 0;
-    if (lane == 0) { stkP = S; stkA = 0; }
-    sp = 1;
-    while (sp > 0 && steps < 2 * kMaxRel) {
-        ++steps;
-        --sp;
-        const uint32_t P = rdlane(stkP, sp);
-        const uint32_t at = rdlane(stkA, sp);
-        const uint32_t cuts = A & P & ~at;
-        if (cuts == 0) {
-            if (lane == nblk) myblk = P;
-            nblk += nblk < kMaxRel - 1 ? 1 : 0;
-            continue;
-        }
-        const uint32_t x = lowbit(cuts);
-        uint32_t rem = P & ~x;
-        while (rem) {
-            const uint32_t K = grow(L.nb, lowbit(rem), rem);
-            rem &= ~K;
-            if (lane == sp) { stkP = K | x; stkA = (at | x) & (K | x); }
-            sp += sp < 63 ? 1 : 0;
+    // 1. depth-first search: k - 1 steps down, k - 1 back up, one final test
+    const uint32_t root = (uint32_t)ctz32(S);
+    uint32_t par = 0, desc = mine ? (1u << lane) : 0u;
+    uint32_t cur = root, seen = 1u << root;
+    for (int step = 0; step < 2 * kMaxRel; ++step) {
+        const uint32_t next = rdlane(adjS, (int)cur) & ~seen;
+        if (next) {
+            const uint32_t c = (uint32_t)ctz32(next);
+            if (lane == (int)c) par = cur;
+            seen |= 1u << c;
+            cur = c;
+        } else {
+            if (cur == root) break;
+            const uint32_t p = rdlane(par, (int)cur);
+            const uint32_t d = rdlane(desc, (int)cur);
+            if (lane == (int)p) desc |= d;
+            cur = p;
         }
     }
 
-    // per-block candidate counts (lane i owns block i)
-    uint32_t chunks = 0, complete = 0;
-    if (lane < nblk) {
+    // 2. lowpoint test, one neighbourhood lookup per lane
+    const bool child = mine && lane != (int)root;
+    const uint32_t outside = child ? (nbrs(L.nb, desc) & S & ~desc) : 0u;
+    const bool top = child && outside == (1u << par);
+    const uint32_t T = (uint32_t)__ballot(top);
+    const uint32_t rootkids = (uint32_t)__popcll(__ballot(child && par == root));
+
+    // 3. blocks and cut vertices
+    uint32_t A = 0, inner = 0;
+    for (uint32_t U = T; U; U &= U - 1) {
+        const uint32_t t = (uint32_t)ctz32(U);
+        A |= 1u << rdlane(par, (int)t);
+        const uint32_t dt = rdlane(desc, (int)t);
+        if (lane != (int)t && ((desc >> t) & 1u)) inner |= dt;
+    }
+    if (rootkids < 2) A &= ~(1u << root);
+    const uint32_t myblk = top ? ((desc & ~inner) | (1u << par)) : 0u;
+
+    // per-block candidates with the lowest relation (a top lane owns its block)
+    uint32_t half = 0, complete = 0;
+    if (top) {
         const int bs = popc32(myblk);
-        const uint32_t half = (1u << (bs - 1)) - 1u;
-        chunks = (half + kEvalChunk - 1) / kEvalChunk;
-        uint32_t deg = 0;
-        for (uint32_t T = myblk; T; T &= T - 1) deg += popc32(L.adj[ctz32(T)] & myblk);
-        complete = deg == (uint32_t)(bs * (bs - 1));
+        half = (1u << (bs - 1)) - 1u;
+        complete = bs <= 3;  // a bridge or a triangle
     }
-    uint32_t acc = 0, mypre = 0;
+    {   // larger blocks: complete iff every member is adjacent to all the others
+        uint32_t d2 = 0;
+        for (uint32_t U = S; U; U &= U - 1) {
+            const int v = ctz32(U);
+            const uint32_t a = rdlane(adjS, v);
+            if ((myblk >> v) & 1u) d2 += (uint32_t)popc32(a & myblk);
+        }
+        const int bs = popc32(myblk);
+        if (top && bs > 3) complete = d2 == (uint32_t)(bs * (bs - 1));
+    }
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+    for (uint32_t U = T; U; U &= U - 1) {
+        const uint32_t h = rdlane(half, ctz32(U));
+        c0 += h;
+        c1 += (h + 1u) >> 1;
+        c2 += (h + 3u) >> 2;
+        c3 += (h + 7u) >> 3;
+        c4 += (h + 15u) >> 4;
+    }
+    const uint32_t shift = c0 <= budget ? 0u : c1 <= budget ? 1u : c2 <= budget ? 2u : c3 <= budget ? 3u : 4u;
+    const uint32_t round = (1u << shift) - 1u;
+    uint32_t acc = 0, idx = 0;
     unsigned long long evaluated = 0;
-    for (int i = 0; i < nblk; ++i) {
-        const uint32_t c = rdlane(chunks, i);
-        if (lane == i) mypre = acc;
-        acc += c;
-        evaluated += (1ull << popc32(rdlane(myblk, i))) - 2ull;
+    for (uint32_t U = T; U; U &= U - 1, ++idx) {
+        const int t = ctz32(U);
+        if (lane == t) { W.blk[idx] = myblk; W.full[idx] = complete; W.cpre[idx] = acc; }
+        acc += (rdlane(half, t) + round) >> shift;
+        evaluated += (1ull << popc32(rdlane(myblk, t))) - 2ull;
     }
-    if (lane < nblk) { W.blk[lane] = myblk; W.full[lane] = complete; W.cpre[lane] = mypre; }
-    if (lane == 0) W.cpre[nblk] = acc;
-    return SetBlocks{A, acc, evaluated};
+    if (lane == 0) W.cpre[idx] = acc;
+    return SetBlocks{A, acc, shift, c4, evaluated};
 }
 
 // Colex ranks of Sl and of S - Sl in one pass over the members of S.
@@ -404,18 +491,19 @@ __device__ __forceinline__ void split_ranks(const LdsGraph &L, uint32_t S, uint3
 // block is); then S_left = grow(lb, S - rb) and S_right = S - S_left.
 template <int CM>
 __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M, const WaveScratch &W, uint32_t S,
-                                            uint32_t A, uint32_t total_chunks, uint32_t first, uint32_t stride,
-                                            double cardS, Key &best, unsigned long long &ccp) {
+                                            const SetBlocks &sb, uint32_t first, uint32_t stride, double cardS,
+                                            Key &best, unsigned long long &ccp) {
     const int k = popc32(S);
-    for (uint32_t ch = first; ch < total_chunks; ch += stride) {
+    const uint32_t A = sb.A;
+    for (uint32_t ch = first; ch < sb.total_chunks; ch += stride) {
         int bi = 0;
         while (W.cpre[bi + 1] <= ch) ++bi;
         const uint32_t b = W.blk[bi];
         const bool full = W.full[bi] != 0;
         const uint32_t lo = lowbit(b), rest = b ^ lo;
         const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
-        const uint32_t j0 = (ch - W.cpre[bi]) * kEvalChunk;
-        const uint32_t j1 = min(j0 + (uint32_t)kEvalChunk, hb);
+        const uint32_t j0 = (ch - W.cpre[bi]) << sb.shift;
+        const uint32_t j1 = min(j0 + (1u << sb.shift), hb);
         uint32_t sub = deposit(j0, rest);
         for (uint32_t j = j0; j < j1; ++j) {
             const uint32_t lb = lo | sub, rb = b ^ lb;
@@ -434,6 +522,70 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
     }
 }
 
+
+// True if the connected set S induces a tree (|S| - 1 edges).
+__device__ __forceinline__ bool induces_tree(const LdsGraph &L, uint32_t S) {
+    uint32_t e2 = 0;
+    for (uint32_t T = S; T; T &= T - 1) e2 += (uint32_t)popc32(L.adj[ctz32(T)] & S);
+    return e2 == 2u * (uint32_t)(popc32(S) - 1);
+}
+
+// Alg. 2 on one connected S whose induced subgraph is a tree, one lane per
+// set: every edge (u, v) of G[S] with u < v gives the pair
+// (grow({u}, S - {v}), the rest), both orientations costed.  The memo
+// gathers of kB pairs are issued before any of them is used.
+template <int CM>
+__device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S,
+                                                  unsigned long long &ccp) {
+    constexpr int kB = 4;
+    const int k = popc32(S);
+    const double cardS = card_of(L, S);
+    Key best = worst_key();
+    uint32_t V = S, U = 0, vbit = 0;
+    while (V | U) {
+        uint32_t Av[kB];
+        uint64_t ia[kB], ib[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            Av[b] = 0;
+            ia[b] = 0;
+            ib[b] = 0;
+            while (!U && V) {
+                vbit = lowbit(V);
+                V ^= vbit;
+                U = L.adj[ctz32(vbit)] & S & (vbit - 1u);
+            }
+            if (U) {
+                const uint32_t ubit = lowbit(U);
+                U ^= ubit;
+                const uint32_t A = grow(L.nb, ubit, S & ~vbit);
+                uint32_t ra, rb;
+                split_ranks(L, S, A, ra, rb);
+                const int ka = popc32(A);
+                Av[b] = A;
+                ia[b] = L.loff[ka] + ra;
+                ib[b] = L.loff[k - ka] + rb;
+            }
+        }
+        double cA[kB], cB[kB], kA[kB], kB2[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            cA[b] = cB[b] = kA[b] = kB2[b] = 0.0;
+            if (!Av[b]) continue;
+            cA[b] = M.cost[ia[b]];
+            cB[b] = M.cost[ib[b]];
+            if (CM != MPDP_COST_COUT) {
+                kA[b] = M.card[ia[b]];
+                kB2[b] = M.card[ib[b]];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b)
+            if (Av[b]) eval_vals<CM>(Av[b], S ^ Av[b], cA[b], cB[b], kA[b], kB2[b], cardS, best);
+    }
+    ccp += (unsigned long long)(k - 1);
+    store_best(M, memo_index(L, S), best, cardS);
+}
 
 __device__ __forceinline__ uint64_t memo_index_t(const uint32_t *binom, const uint64_t *loff, uint32_t T) {
     uint32_t r = 0;
@@ -502,40 +654,96 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
 }
 
 // One wave's share of the unrank + filter step for the block-based path:
-// kFilterChunk consecutive colex ranks per lane; the wave compacts its
-// connected sets in rank order (each lane's count is prefixed across the
-// wave with one ballot per count bit) and one atomic on `count` (global or
-// LDS) reserves the output range in `list`.
+// kFilterChunk consecutive colex ranks per lane.  The connected sets that
+// induce a tree are appended at the front of `list` (count in *ntree), the
+// others at its back, from list[cap - 1] downwards (count in *ngen); each
+// lane's counts are prefixed across the wave with one ballot per count bit
+// and one atomic per list and wave (global or LDS) reserves the range.
 __device__ void filter_wave(const LdsGraph &L, int n, uint32_t k, uint64_t ncand, uint64_t w0, uint64_t wstride,
-                            uint32_t *list, uint32_t *count, uint32_t lane) {
+                            uint32_t *list, uint32_t cap, uint32_t *ntree, uint32_t *ngen, uint32_t lane) {
     const unsigned long long below_me = (1ull << lane) - 1ull;
     const uint64_t per_wave = 64ull * kFilterChunk;
     for (uint64_t w = w0; w * per_wave < ncand; w += wstride) {
         const uint64_t r0 = w * per_wave + (uint64_t)lane * kFilterChunk;
         uint32_t S = r0 < ncand ? colex_unrank(L.binom, n, (int)k, (uint32_t)r0) : 0u;
         uint32_t sets[kFilterChunk];
-        uint32_t keep = 0;
+        uint32_t keep_t = 0, keep_g = 0;
 #pragma unroll
         for (int j = 0; j < kFilterChunk; ++j) {
             sets[j] = S;
             if (r0 + (uint64_t)j < ncand) {
-                if (grow(L.nb, lowbit(S), S) == S) keep |= 1u << j;
+                if (grow(L.nb, lowbit(S), S) == S) {
+                    if (induces_tree(L, S)) keep_t |= 1u << j;
+                    else keep_g |= 1u << j;
+                }
                 S = next_subset(S);
             }
         }
-        const uint32_t mine = (uint32_t)popc32(keep);
-        uint32_t before = 0;
+        const uint32_t mt = (uint32_t)popc32(keep_t), mg = (uint32_t)popc32(keep_g);
+        uint32_t bt = 0, bg = 0;
 #pragma unroll
-        for (int b = 0; b < 5; ++b)  // exclusive prefix of `mine` (<= 16) across the wave
-            before += (uint32_t)__popcll(__ballot((mine >> b) & 1u) & below_me) << b;
-        const uint32_t total = (uint32_t)__shfl((int)(before + mine), 63);
-        if (total == 0) continue;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(count, total);
-        base = (uint32_t)__shfl((int)base, 0) + before;
+        for (int b = 0; b < 5; ++b) {  // exclusive prefixes (counts <= 16) across the wave
+            bt += (uint32_t)__popcll(__ballot((mt >> b) & 1u) & below_me) << b;
+            bg += (uint32_t)__popcll(__ballot((mg >> b) & 1u) & below_me) << b;
+        }
+        const uint32_t tot_t = (uint32_t)__shfl((int)(bt + mt), 63);
+        const uint32_t tot_g = (uint32_t)__shfl((int)(bg + mg), 63);
+        if (tot_t) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(ntree, tot_t);
+            base = (uint32_t)__shfl((int)base, 0) + bt;
 #pragma unroll
-        for (int j = 0; j < kFilterChunk; ++j)
-            if (keep & (1u << j)) list[base++] = sets[j];
+            for (int j = 0; j < kFilterChunk; ++j)
+                if (keep_t & (1u << j)) list[base++] = sets[j];
+        }
+        if (tot_g) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(ngen, tot_g);
+            base = (uint32_t)__shfl((int)base, 0) + bg;
+#pragma unroll
+            for (int j = 0; j < kFilterChunk; ++j)
+                if (keep_g & (1u << j)) list[cap - 1u - base++] = sets[j];
+        }
+    }
+}
+
+// One wave's share of the light work of a block-based level.  Work item i
+// (i = w0, w0 + wstride, ...) is either a group of 64 tree-inducing sets
+// from the front of `list`, one per lane (Alg. 2 on G[S]), or, past the
+// groups, one other set from the back of `list`, taken by the whole wave
+// (Alg. 3 over its blocks).  A set with more than kHeavyChunks 16-candidate
+// chunks is appended to `heavy` for a whole workgroup instead.
+template <int CM>
+__device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *list, uint32_t cap, uint32_t ntree,
+                           uint32_t ngen, uint32_t w0, uint32_t wstride, WaveScratch &W, uint32_t *heavy,
+                           uint32_t *nheavy, uint32_t lane, unsigned long long &ccp, unsigned long long &evaluated) {
+    const uint32_t groups = (ntree + 63u) >> 6;
+    for (uint32_t i = w0; i < groups + ngen; i += wstride) {
+        if (i < groups) {
+            const uint32_t idx = (i << 6) + lane;
+            if (idx < ntree) {
+                const uint32_t S = list[idx];
+                eval_treelike_set<CM>(L, M, S, ccp);
+                evaluated += 2ull * (unsigned long long)(popc32(S) - 1);
+            }
+            continue;
+        }
+        const uint32_t S = list[cap - 1u - (i - groups)];
+        const SetBlocks sb = analyze_set(L, S, W, (int)lane, 64u);
+        if (sb.chunks16 > kHeavyChunks) {
+            if (lane == 0) heavy[atomicAdd(nheavy, 1u)] = S;
+            wave_sync_lds();
+            continue;
+        }
+        if (lane == 0) evaluated += sb.evaluated;
+        wave_sync_lds();
+        const double cardS = card_of_wave(L, S, lane);
+        Key best = worst_key();
+        eval_chunks<CM>(L, M, W, S, sb, lane, 64u, cardS, best, ccp);
+        best = wave_min(best);
+        const uint64_t at = memo_index_wave(L, S, lane);
+        if (lane == 0) store_best(M, at, best, cardS);
+        wave_sync_lds();
     }
 }
 

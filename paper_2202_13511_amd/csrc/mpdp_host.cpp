@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "mpdp.h"
+#include "mpdp_host_internal.h"
 #include "mpdp_internal.h"
 
 namespace {
@@ -59,9 +60,11 @@ struct Query {
     DevGraph g;
 };
 
-// Validation runs entirely on the host, before any HIP call.
+// Validation runs entirely on the host, before any HIP call.  base_costs
+// (may be null) gives each relation the cost of an already planned
+// intermediate result instead of its scan.
 mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *card, const double *sel,
-                     mpdp_cost_model cm, Query &q) {
+                     mpdp_cost_model cm, const double *base_costs, Query &q) {
     if (n == 0) return MPDP_EINVAL;
     if (n > 32) return MPDP_ETOOLARGE;
     if (cm != MPDP_COST_COUT && cm != MPDP_COST_PGLIKE) return MPDP_EINVAL;
@@ -79,7 +82,12 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
     for (uint32_t v = 0; v < n; ++v) {
         if (!std::isfinite(card[v]) || !(card[v] >= 1.0)) return MPDP_EINVAL;
         L.card[v] = card[v];
-        L.bcost[v] = (cm == MPDP_COST_PGLIKE) ? 0.01 * card[v] : 0.0;
+        if (base_costs) {
+            if (!std::isfinite(base_costs[v]) || !(base_costs[v] >= 0.0)) return MPDP_EINVAL;
+            L.bcost[v] = base_costs[v];
+        } else {
+            L.bcost[v] = (cm == MPDP_COST_PGLIKE) ? 0.01 * card[v] : 0.0;
+        }
     }
     for (uint32_t i = 0; i < m; ++i) {
         const uint32_t u = edges[i].u, v = edges[i].v;
@@ -239,7 +247,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         st.candidates = candidates;
         uint64_t conn = 0, tree_ccp = 0;
         for (uint32_t k = 2; k <= n; ++k) {
-            conn += hc.level_count[k];
+            conn += hc.level_count[k] + hc.general_count[k];
             tree_ccp += (uint64_t)(k - 1) * hc.level_count[k];
         }
         st.connected_sets = conn;
@@ -276,7 +284,7 @@ constexpr uint32_t kFlagForceGeneral = 0x100u;
 // ---------------------------------------------------------------- batch
 
 struct BatchLayout {
-    size_t binom, counters, queries, edges, cards, sels, plans, out, slots, slot_bytes, total;
+    size_t binom, counters, queries, edges, cards, sels, bcosts, plans, out, slots, slot_bytes, total;
     uint32_t workgroups, maxn;
     uint64_t sum_m, sum_n, sum_nodes;
 };
@@ -301,6 +309,7 @@ bool batch_layout(uint32_t nq, const mpdp_batch_query *qs, BatchLayout &B) {
     B.edges = o;    o = align_up(o + 8 * B.sum_m);
     B.cards = o;    o = align_up(o + 8 * B.sum_n);
     B.sels = o;     o = align_up(o + 8 * B.sum_m);
+    B.bcosts = o;   o = align_up(o + 8 * B.sum_n);
     B.plans = o;    o = align_up(o + sizeof(mpdp_plan_node) * B.sum_nodes);
     B.out = o;      o = align_up(o + sizeof(mpdp::BatchOut) * nq);
     const uint64_t N = 1ull << maxn;
@@ -312,7 +321,7 @@ bool batch_layout(uint32_t nq, const mpdp_batch_query *qs, BatchLayout &B) {
 
 // Host validation of one batch query (same rules as mpdp_optimize).
 mpdp_status validate_batch_query(const mpdp_batch_query &Q, const mpdp_edge *edges, const double *card,
-                                 const double *sel) {
+                                 const double *sel, const double *bcost) {
     const uint32_t n = Q.n, m = Q.m;
     if (n == 0) return MPDP_EINVAL;
     if (n > mpdp::kBatchMaxRel) return MPDP_ETOOLARGE;
@@ -321,6 +330,8 @@ mpdp_status validate_batch_query(const mpdp_batch_query &Q, const mpdp_edge *edg
     for (uint32_t v = 0; v < n; ++v) {
         const double c = card[Q.card_offset + v];
         if (!std::isfinite(c) || !(c >= 1.0)) return MPDP_EINVAL;
+        if (bcost && (!std::isfinite(bcost[Q.card_offset + v]) || !(bcost[Q.card_offset + v] >= 0.0)))
+            return MPDP_EINVAL;
     }
     for (uint32_t i = 0; i < m; ++i) {
         const mpdp_edge e = edges[Q.edge_offset + i];
@@ -342,20 +353,11 @@ mpdp_status validate_batch_query(const mpdp_batch_query &Q, const mpdp_edge *edg
     return seen == full ? MPDP_OK : MPDP_ENOTCONNECTED;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t mpdp_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries) {
-    BatchLayout B;
-    return batch_layout(nq, queries, B) ? B.total : 0;
-}
-
-mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
-                                const double *cardinalities, const double *selectivities,
-                                mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
-                                uint32_t flags, mpdp_plan_node *plans_out, double *costs_out,
-                                double *latency_us_out, double *start_us_out, mpdp_batch_stats *stats_out) {
+mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                       const double *cardinalities, const double *selectivities, const double *base_costs,
+                       mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                       uint32_t flags, mpdp_plan_node *plans_out, double *costs_out, double *latency_us_out,
+                       double *start_us_out, mpdp_batch_stats *stats_out) {
     const double t0 = now_ms();
     if (nq == 0 || !queries || !cardinalities || !plans_out || !costs_out) return MPDP_EINVAL;
     if (cost_model != MPDP_COST_COUT && cost_model != MPDP_COST_PGLIKE) return MPDP_EINVAL;
@@ -363,7 +365,7 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
     for (uint32_t i = 0; i < nq; ++i) sum_m += queries[i].m;
     if (sum_m > 0 && (!edges || !selectivities)) return MPDP_EINVAL;
     for (uint32_t i = 0; i < nq; ++i) {
-        const mpdp_status st = validate_batch_query(queries[i], edges, cardinalities, selectivities);
+        const mpdp_status st = validate_batch_query(queries[i], edges, cardinalities, selectivities, base_costs);
         if (st != MPDP_OK) return st;
     }
     BatchLayout B;
@@ -387,6 +389,7 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
     uint32_t *de = reinterpret_cast<uint32_t *>(up.data() + B.edges);
     double *dc = reinterpret_cast<double *>(up.data() + B.cards);
     double *ds = reinterpret_cast<double *>(up.data() + B.sels);
+    double *db = reinterpret_cast<double *>(up.data() + B.bcosts);
     // descriptors in the order the workgroups take them: larger queries first
     std::vector<uint32_t> order(nq);
     for (uint32_t i = 0; i < nq; ++i) order[i] = i;
@@ -403,7 +406,10 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
         const mpdp_batch_query &Q = queries[i];
         const uint64_t po = plan_at[i];
         dq[j] = mpdp::BatchQueryDev{Q.n, Q.m, Q.m == Q.n - 1 ? 1u : 0u, (uint32_t)cost_model, co, eo, po};
-        for (uint32_t v = 0; v < Q.n; ++v) dc[co + v] = cardinalities[Q.card_offset + v];
+        for (uint32_t v = 0; v < Q.n; ++v) {
+            dc[co + v] = cardinalities[Q.card_offset + v];
+            db[co + v] = base_costs ? base_costs[Q.card_offset + v] : 0.0;
+        }
         for (uint32_t e = 0; e < Q.m; ++e) {
             de[2 * (eo + e)] = edges[Q.edge_offset + e].u;
             de[2 * (eo + e) + 1] = edges[Q.edge_offset + e].v;
@@ -423,6 +429,7 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
     HIPCHK(mpdp::launch_batch(cost_model, B.workgroups, reinterpret_cast<mpdp::BatchQueryDev *>(base + B.queries),
                               nq, reinterpret_cast<uint32_t *>(base + B.edges),
                               reinterpret_cast<double *>(base + B.cards), reinterpret_cast<double *>(base + B.sels),
+                              base_costs ? reinterpret_cast<double *>(base + B.bcosts) : nullptr,
                               reinterpret_cast<uint32_t *>(base + B.binom), base + B.slots, B.slot_bytes, B.maxn,
                               reinterpret_cast<mpdp_plan_node *>(base + B.plans),
                               reinterpret_cast<mpdp::BatchOut *>(base + B.out),
@@ -461,6 +468,55 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
     return MPDP_OK;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------- exact step for the large-query heuristics
+
+namespace mpdp_host {
+
+size_t units_workspace_bytes(uint32_t n) { return (n == 0 || n > 32) ? 0 : make_layout(n).total; }
+
+size_t units_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries) {
+    BatchLayout B;
+    return batch_layout(nq, queries, B) ? B.total : 0;
+}
+
+mpdp_status optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *card, const double *sel,
+                           const double *base_costs, mpdp_cost_model cm, void *d_ws, size_t ws_bytes,
+                           hipStream_t s, mpdp_plan_node *plan_out, double *cost_out) {
+    const double t0 = now_ms();
+    Query q;
+    mpdp_status st = validate(n, m, edges, card, sel, cm, base_costs, q);
+    if (st != MPDP_OK) return st;
+    if (n == 1) return leaf_only(q, plan_out, cost_out);
+    return run(q, d_ws, ws_bytes, s, 0, plan_out, cost_out, nullptr, t0, false);
+}
+
+mpdp_status optimize_units_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                 const double *card, const double *sel, const double *base_costs,
+                                 mpdp_cost_model cm, void *d_ws, size_t ws_bytes, hipStream_t s,
+                                 mpdp_plan_node *plans_out, double *costs_out) {
+    return batch_core(nq, queries, edges, card, sel, base_costs, cm, d_ws, ws_bytes, s, 0, plans_out, costs_out,
+                      nullptr, nullptr, nullptr);
+}
+
+}  // namespace mpdp_host
+
+extern "C" {
+
+size_t mpdp_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries) {
+    BatchLayout B;
+    return batch_layout(nq, queries, B) ? B.total : 0;
+}
+
+mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                                uint32_t flags, mpdp_plan_node *plans_out, double *costs_out,
+                                double *latency_us_out, double *start_us_out, mpdp_batch_stats *stats_out) {
+    return batch_core(nq, queries, edges, cardinalities, selectivities, nullptr, cost_model, d_workspace, ws_bytes,
+                      hip_stream, flags, plans_out, costs_out, latency_us_out, start_us_out, stats_out);
+}
 
 const char *mpdp_status_str(mpdp_status s) {
     switch (s) {
@@ -497,7 +553,7 @@ mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges, con
     const double t0 = now_ms();
     if (!plan_out || !cost_out) return MPDP_EINVAL;
     Query q;
-    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, q);
+    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, nullptr, q);
     if (st != MPDP_OK) return st;
     if (n == 1) {
         st = leaf_only(q, plan_out, cost_out);
@@ -512,13 +568,35 @@ mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges, con
                stats_out, t0, (flags & kFlagForceGeneral) != 0);
 }
 
+mpdp_status mpdp_optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,
+                                const double *selectivities, const double *base_costs, mpdp_cost_model cost_model,
+                                void *d_workspace, size_t ws_bytes, void *hip_stream, uint32_t flags,
+                                mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!plan_out || !cost_out || !base_costs) return MPDP_EINVAL;
+    Query q;
+    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, base_costs, q);
+    if (st != MPDP_OK) return st;
+    if (n == 1) {
+        st = leaf_only(q, plan_out, cost_out);
+        if (stats_out) {
+            std::memset(stats_out, 0, sizeof(*stats_out));
+            stats_out->ms_total = now_ms() - t0;
+        }
+        return st;
+    }
+    if (!d_workspace) return MPDP_EINVAL;
+    return run(q, d_workspace, ws_bytes, static_cast<hipStream_t>(hip_stream), flags, plan_out, cost_out,
+               stats_out, t0, false);
+}
+
 mpdp_status mpdp_optimize(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,
                           const double *selectivities, mpdp_cost_model cost_model, mpdp_plan_node *plan_out,
                           double *cost_out, mpdp_stats *stats_out) {
     const double t0 = now_ms();
     if (!plan_out || !cost_out) return MPDP_EINVAL;
     Query q;
-    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, q);
+    mpdp_status st = validate(n, m, edges, cardinalities, selectivities, cost_model, nullptr, q);
     if (st != MPDP_OK) return st;
     if (n == 1) {
         st = leaf_only(q, plan_out, cost_out);

@@ -1,0 +1,25 @@
+// Host-side exact step for the large-query heuristics (mpdp_large.cpp):
+// MPDP on a query whose relations are units (base relations or planned
+// intermediate results, each with its plan's cost), one query at a time or
+// many at once through the batched kernel.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mpdp.h"
+
+namespace mpdp_host {
+
+size_t units_workspace_bytes(uint32_t n);
+size_t units_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries);
+
+mpdp_status optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *card, const double *sel,
+                           const double *base_costs, mpdp_cost_model cm, void *d_ws, size_t ws_bytes,
+                           hipStream_t s, mpdp_plan_node *plan_out, double *cost_out);
+
+mpdp_status optimize_units_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                 const double *card, const double *sel, const double *base_costs,
+                                 mpdp_cost_model cm, void *d_ws, size_t ws_bytes, hipStream_t s,
+                                 mpdp_plan_node *plans_out, double *costs_out);
+
+}  // namespace mpdp_host

@@ -50,7 +50,8 @@ struct MemoPtrs {
 
 // Device-side counters, cleared by the init kernel.
 struct Counters {
-    uint32_t level_count[34];   // connected sets found at each level
+    uint32_t level_count[34];   // connected sets found at each level (block-based path: those inducing a tree)
+    uint32_t general_count[34]; // block-based path: the other connected sets of each level
     uint32_t heavy_count[34];   // sets handed to the heavy kernel at each level
     uint32_t extract_error;     // nonzero if plan extraction met an inconsistent memo
     uint32_t pad;
@@ -80,8 +81,9 @@ constexpr uint32_t kBatchMaxRel = 20;      // largest query the batched path tak
 constexpr uint32_t kBatchWorkgroups = 512; // persistent workgroups (two per CU)
 
 hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs, uint32_t nq,
-                        const uint32_t *edges, const double *cards, const double *sels, const uint32_t *binom,
-                        char *slots, uint64_t slot_bytes, uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
+                        const uint32_t *edges, const double *cards, const double *sels, const double *bcosts,
+                        const uint32_t *binom, char *slots, uint64_t slot_bytes, uint32_t maxn,
+                        mpdp_plan_node *plans, BatchOut *out,
                         BatchCounters *bc, hipStream_t s);
 
 hipError_t launch_init(const DevGraph *g, uint32_t n, MemoPtrs memo, Counters *cnt, hipStream_t s);

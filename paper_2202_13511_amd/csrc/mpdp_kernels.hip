@@ -56,48 +56,33 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
 
-// Unrank + filter for the block kernel.  Each lane takes kFilterChunk
-// consecutive colex ranks; the wave compacts its connected sets in rank
-// order (each lane's count is prefixed across the wave with one ballot per
-// count bit) and one atomic per wave reserves the output range.
+// Unrank + filter of a block-based level: kFilterChunk consecutive colex
+// ranks per lane; sets that induce a tree go to the front of the list, the
+// other connected sets to its back.
 __global__ __launch_bounds__(kBlock) void k_filter(const DevGraph *g, uint32_t k, uint64_t ncand,
                                                    uint32_t *list, Counters *cnt) {
     __shared__ __align__(16) LdsGraph L;
     stage_graph(g, L);
-    filter_wave(L, (int)g->n, k, ncand, (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6),
-                (uint64_t)gridDim.x * kWaves, list, &cnt->level_count[k], threadIdx.x & 63u);
+    const uint32_t n = g->n;
+    filter_wave(L, (int)n, k, ncand, (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6),
+                (uint64_t)gridDim.x * kWaves, list, L.binom[n * 33 + n / 2], &cnt->level_count[k],
+                &cnt->general_count[k], threadIdx.x & 63u);
 }
 
-// Alg. 3, light sets: one wave64 per connected S.  A set with more than
-// kHeavyChunks candidate chunks is handed to k_eval_heavy instead.
+// Light work of a block-based level: groups of 64 tree-inducing sets, one
+// per lane, then one wave64 per other set.  A set with more than
+// kHeavyChunks 16-candidate chunks is handed to k_eval_heavy instead.
 template <int CM>
 __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint32_t k, const uint32_t *list,
                                                          uint32_t *heavy, Counters *cnt, MemoPtrs M) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ WaveScratch WS[kWaves];
     stage_graph(g, L);
-    const int lane = threadIdx.x & 63;
-    WaveScratch &W = WS[threadIdx.x >> 6];
-    const uint32_t count = cnt->level_count[k];
+    const uint32_t lane = threadIdx.x & 63u, n = g->n;
     unsigned long long my_ccp = 0, my_eval = 0;
-
-    for (uint32_t idx = blockIdx.x * kWaves + (threadIdx.x >> 6); idx < count; idx += gridDim.x * kWaves) {
-        const uint32_t S = list[idx];
-        const SetBlocks sb = analyze_set(L, S, W, lane);
-        if (sb.total_chunks > kHeavyChunks) {
-            if (lane == 0) heavy[atomicAdd(&cnt->heavy_count[k], 1u)] = S;
-            wave_sync_lds();
-            continue;
-        }
-        if (lane == 0) my_eval += sb.evaluated;
-        wave_sync_lds();
-        const double cardS = card_of(L, S);
-        Key best = worst_key();
-        eval_chunks<CM>(L, M, W, S, sb.A, sb.total_chunks, (uint32_t)lane, 64u, cardS, best, my_ccp);
-        best = wave_min(best);
-        if (lane == 0) store_best(M, memo_index(L, S), best, cardS);
-        wave_sync_lds();
-    }
+    light_sets<CM>(L, M, list, L.binom[n * 33 + n / 2], cnt->level_count[k], cnt->general_count[k],
+                   blockIdx.x * kWaves + (threadIdx.x >> 6), gridDim.x * kWaves, WS[threadIdx.x >> 6], heavy,
+                   &cnt->heavy_count[k], lane, my_ccp, my_eval);
 
     // one atomic per wave for the counters
     for (int off = 32; off >= 1; off >>= 1) {
@@ -128,14 +113,14 @@ __global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, u
     for (uint32_t h = blockIdx.x; h < count; h += gridDim.x) {
         const uint32_t S = heavy[h];
         if (wave == 0) {
-            const SetBlocks sb = analyze_set(L, S, W, lane);
+            const SetBlocks sb = analyze_set(L, S, W, lane, kHeavyBlock);
             if (lane == 0) { sbs = sb; my_eval += sb.evaluated; }
         }
         __syncthreads();
         const SetBlocks sb = sbs;
-        const double cardS = card_of(L, S);
+        const double cardS = card_of_wave(L, S, threadIdx.x & 63u);
         Key best = worst_key();
-        eval_chunks<CM>(L, M, W, S, sb.A, sb.total_chunks, threadIdx.x, kHeavyBlock, cardS, best, my_ccp);
+        eval_chunks<CM>(L, M, W, S, sb, threadIdx.x, kHeavyBlock, cardS, best, my_ccp);
         best = wave_min(best);
         if (lane == 0) keys[wave] = best;
         __syncthreads();

@@ -1,0 +1,699 @@
+// Large-query heuristics of Section 4 on the host, with this library's
+// exact DP on the GPU as the inner step: GOO, IDP2 with GOO's plan as its
+// start (Section 4.1) and UnionDP (Section 4.2, Alg. 4).  The conventions
+// the paper leaves open (card of large sets, re-costing, units, tie-breaks,
+// the union order) are stated at mpdp_optimize_large in include/mpdp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <queue>
+#include <set>
+#include <tuple>
+#include <unordered_set>
+#include <vector>
+
+#include "mpdp.h"
+#include "mpdp_host_internal.h"
+
+namespace {
+
+constexpr uint32_t kLargeMaxRel = 4096;
+constexpr uint32_t kLargeMaxK = 25;
+constexpr uint32_t kBatchUnits = 20;  // parts of at most this many units go through the batched kernel
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------- relation sets of any size
+
+struct Bits {
+    std::vector<uint64_t> w;
+    Bits() = default;
+    explicit Bits(size_t words) : w(words, 0ull) {}
+    void set(uint32_t v) { w[v >> 6] |= 1ull << (v & 63u); }
+    bool has(uint32_t v) const { return (w[v >> 6] >> (v & 63u)) & 1ull; }
+    Bits operator|(const Bits &o) const {
+        Bits r(w.size());
+        for (size_t i = 0; i < w.size(); ++i) r.w[i] = w[i] | o.w[i];
+        return r;
+    }
+    uint32_t lowest() const {
+        for (size_t i = 0; i < w.size(); ++i)
+            if (w[i]) return (uint32_t)(64 * i + __builtin_ctzll(w[i]));
+        return ~0u;
+    }
+    uint32_t count() const {
+        uint32_t c = 0;
+        for (uint64_t x : w) c += (uint32_t)__builtin_popcountll(x);
+        return c;
+    }
+    template <class F>
+    void each(F f) const {  // ascending
+        for (size_t i = 0; i < w.size(); ++i)
+            for (uint64_t x = w[i]; x; x &= x - 1) f((uint32_t)(64 * i + __builtin_ctzll(x)));
+    }
+};
+
+// a < b as binary numbers
+bool bits_less(const Bits &a, const Bits &b) {
+    for (size_t i = a.w.size(); i-- > 0;)
+        if (a.w[i] != b.w[i]) return a.w[i] < b.w[i];
+    return false;
+}
+
+// ---------------------------------------------------------------- query
+
+struct Graph {
+    uint32_t n = 0, words = 0;
+    int cm = 0;
+    std::vector<double> card;
+    std::vector<uint32_t> eu, ev;  // edge list order
+    std::vector<double> sel;
+    std::vector<std::vector<std::pair<uint32_t, double>>> lower;  // per v: (u, sel) of edges (u, v), u < v, u ascending
+    std::vector<std::vector<uint32_t>> adj;
+
+    Bits single(uint32_t v) const {
+        Bits b(words);
+        b.set(v);
+        return b;
+    }
+    // card(S): the canonical product of the exact DP, for a set of any size
+    double card_of(const Bits &S) const {
+        double c = 1.0;
+        S.each([&](uint32_t v) {
+            c = c * card[v];
+            for (const auto &us : lower[v])
+                if (S.has(us.first)) c = c * us.second;
+        });
+        return c < 1.0 ? 1.0 : c;
+    }
+    double scan_cost(uint32_t v) const { return cm == MPDP_COST_PGLIKE ? 0.01 * card[v] : 0.0; }
+};
+
+// ---------------------------------------------------------------- plans and their re-costing
+
+struct PNode {
+    int a = -1, b = -1;  // join children, or -1
+    int leaf = -1;       // relation of a leaf
+    bool done = false;   // re-costed
+    Bits rels;
+    double cost = 0.0, card = 0.0;
+    uint32_t op = MPDP_OP_SCAN;
+    int l = -1, r = -1;  // chosen orientation
+};
+
+struct Side {
+    const Bits *rels;
+    double cost, card;
+};
+
+// One join of the re-costing: cheaper orientation and operator; key (cost,
+// left relation set as a binary number, HASH before NESTLOOP).
+void combine(int cm, const Side &a, const Side &b, double cS, double &cost, uint32_t &op, bool &a_left) {
+    const double base = a.cost + b.cost;
+    if (cm == MPDP_COST_COUT) {
+        cost = base + cS;
+        op = MPDP_OP_JOIN;
+        a_left = bits_less(*a.rels, *b.rels);
+        return;
+    }
+    const double out = 0.01 * cS;
+    double c[2];
+    uint32_t o[2];
+    const Side *L[2] = {&a, &b}, *R[2] = {&b, &a};
+    for (int i = 0; i < 2; ++i) {
+        const double hj = ((base + 0.0125 * R[i]->card) + 0.0025 * L[i]->card) + out;
+        const double nl = (base + (0.0025 * L[i]->card) * R[i]->card) + out;
+        if (hj <= nl) { c[i] = hj; o[i] = MPDP_OP_HASH; }
+        else { c[i] = nl; o[i] = MPDP_OP_NESTLOOP; }
+    }
+    bool first;
+    if (c[0] != c[1]) first = c[0] < c[1];
+    else first = bits_less(*a.rels, *b.rels);  // the two left sets differ: op is not reached
+    cost = first ? c[0] : c[1];
+    op = first ? o[0] : o[1];
+    a_left = first;
+}
+
+struct Pool {
+    const Graph *G;
+    std::vector<PNode> nodes;
+    std::vector<int> leaf_of;
+
+    int leaf(uint32_t v) {
+        if (leaf_of[v] >= 0) return leaf_of[v];
+        PNode p;
+        p.leaf = (int)v;
+        nodes.push_back(std::move(p));
+        return leaf_of[v] = (int)nodes.size() - 1;
+    }
+    int join(int a, int b) {
+        PNode p;
+        p.a = a;
+        p.b = b;
+        nodes.push_back(std::move(p));
+        return (int)nodes.size() - 1;
+    }
+    // bottom-up re-costing over the base relations, memoised per node
+    void recost(int id) {
+        // explicit post-order: trees may be as deep as they are wide
+        std::vector<std::pair<int, bool>> st{{id, false}};
+        while (!st.empty()) {
+            auto [x, expanded] = st.back();
+            st.pop_back();
+            PNode &p = nodes[x];
+            if (p.done) continue;
+            if (p.leaf >= 0) {
+                p.rels = G->single((uint32_t)p.leaf);
+                p.cost = G->scan_cost((uint32_t)p.leaf);
+                p.card = G->card[p.leaf];
+                p.op = MPDP_OP_SCAN;
+                p.done = true;
+                continue;
+            }
+            if (!expanded) {
+                st.push_back({x, true});
+                st.push_back({p.b, false});
+                st.push_back({p.a, false});
+                continue;
+            }
+            const PNode &A = nodes[p.a], &B = nodes[p.b];
+            Bits S = A.rels | B.rels;
+            const double cS = G->card_of(S);
+            double cost;
+            uint32_t op;
+            bool a_left;
+            combine(G->cm, Side{&A.rels, A.cost, A.card}, Side{&B.rels, B.cost, B.card}, cS, cost, op, a_left);
+            PNode &q = nodes[x];  // (no reallocation happens inside this loop)
+            q.rels = std::move(S);
+            q.card = cS;
+            q.cost = cost;
+            q.op = op;
+            q.l = a_left ? q.a : q.b;
+            q.r = a_left ? q.b : q.a;
+            q.done = true;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- exact step on units
+
+struct Unit {
+    Bits rels;
+    int plan;
+    uint32_t low;
+};
+
+struct ExactCtx {
+    const Graph *G;
+    Pool *P;
+    hipStream_t s;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<int> where;  // relation -> local unit index, -1 outside
+    mpdp_large_stats st{};
+
+    ~ExactCtx() {
+        if (ws) (void)hipFree(ws);
+    }
+    mpdp_status reserve(size_t bytes) {
+        if (bytes <= ws_bytes) return MPDP_OK;
+        if (ws) {
+            if (hipFree(ws) != hipSuccess) return MPDP_EDEVICE;
+            ws = nullptr;
+            ws_bytes = 0;
+        }
+        if (hipMalloc(&ws, bytes) != hipSuccess || !ws) {
+            (void)hipGetLastError();
+            ws = nullptr;
+            return MPDP_ENOMEM;
+        }
+        ws_bytes = bytes;
+        return MPDP_OK;
+    }
+};
+
+struct UnitQuery {
+    std::vector<const Unit *> us;  // labelled by lowest relation
+    std::vector<mpdp_edge> edges;
+    std::vector<double> card, sel, bcost;
+};
+
+void build_unit_query(ExactCtx &X, const std::vector<const Unit *> &units, UnitQuery &Q) {
+    const Graph &G = *X.G;
+    Q.us = units;
+    std::sort(Q.us.begin(), Q.us.end(), [](const Unit *a, const Unit *b) { return a->low < b->low; });
+    for (size_t i = 0; i < Q.us.size(); ++i) Q.us[i]->rels.each([&](uint32_t v) { X.where[v] = (int)i; });
+    std::map<std::pair<uint32_t, uint32_t>, double> cross;
+    for (size_t e = 0; e < G.eu.size(); ++e) {
+        const int a = X.where[G.eu[e]], b = X.where[G.ev[e]];
+        if (a < 0 || b < 0 || a == b) continue;
+        const auto key = std::make_pair((uint32_t)std::min(a, b), (uint32_t)std::max(a, b));
+        auto it = cross.find(key);
+        if (it == cross.end()) cross.emplace(key, 1.0 * G.sel[e]);
+        else it->second = it->second * G.sel[e];
+    }
+    for (const auto &kv : cross) {
+        Q.edges.push_back(mpdp_edge{kv.first.first, kv.first.second});
+        Q.sel.push_back(kv.second < DBL_MIN ? DBL_MIN : kv.second);
+    }
+    for (const Unit *u : Q.us) {
+        Q.card.push_back(G.card_of(u->rels));
+        X.P->recost(u->plan);
+        Q.bcost.push_back(X.P->nodes[u->plan].cost);
+    }
+    for (const Unit *u : Q.us) u->rels.each([&](uint32_t v) { X.where[v] = -1; });
+}
+
+// The DP's plan over units, rebuilt as a plan over base relations.
+int plan_from_units(Pool &P, const UnitQuery &Q, const mpdp_plan_node *plan) {
+    const uint32_t j = (uint32_t)Q.us.size();
+    std::vector<int> id(2 * j - 1);
+    for (uint32_t i = 0; i < j; ++i) id[i] = Q.us[i]->plan;
+    for (uint32_t i = j; i < 2 * j - 1; ++i) id[i] = P.join(id[plan[i].left], id[plan[i].right]);
+    return id[2 * j - 2];
+}
+
+// Plan each group of units exactly; returns the new plans in group order.
+mpdp_status exact_groups(ExactCtx &X, const std::vector<std::vector<const Unit *>> &groups, std::vector<int> &out) {
+    out.assign(groups.size(), -1);
+    std::vector<UnitQuery> qs(groups.size());
+    std::vector<size_t> todo_batch, todo_single;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        if (groups[g].size() == 1) {
+            out[g] = groups[g][0]->plan;
+            continue;
+        }
+        build_unit_query(X, groups[g], qs[g]);
+        X.st.exact_calls += 1;
+        X.st.exact_units += groups[g].size();
+        X.st.max_units = std::max<uint32_t>(X.st.max_units, (uint32_t)groups[g].size());
+        if (groups[g].size() <= kBatchUnits) todo_batch.push_back(g);
+        else todo_single.push_back(g);
+    }
+    const double t0 = now_ms();
+    const mpdp_cost_model cm = (mpdp_cost_model)X.G->cm;
+    if (todo_batch.size() == 1) todo_single.insert(todo_single.begin(), todo_batch[0]), todo_batch.clear();
+    if (!todo_batch.empty()) {
+        std::vector<mpdp_batch_query> bq;
+        std::vector<mpdp_edge> e;
+        std::vector<double> c, s, b;
+        uint64_t nodes = 0;
+        for (size_t g : todo_batch) {
+            const UnitQuery &Q = qs[g];
+            bq.push_back(mpdp_batch_query{(uint32_t)Q.us.size(), (uint32_t)Q.edges.size(), (uint32_t)c.size(),
+                                          (uint32_t)e.size()});
+            e.insert(e.end(), Q.edges.begin(), Q.edges.end());
+            s.insert(s.end(), Q.sel.begin(), Q.sel.end());
+            c.insert(c.end(), Q.card.begin(), Q.card.end());
+            b.insert(b.end(), Q.bcost.begin(), Q.bcost.end());
+            nodes += 2 * Q.us.size() - 1;
+        }
+        const size_t bytes = mpdp_host::units_batch_workspace_bytes((uint32_t)bq.size(), bq.data());
+        if (bytes == 0) return MPDP_EINVAL;
+        mpdp_status st = X.reserve(bytes);
+        if (st != MPDP_OK) return st;
+        std::vector<mpdp_plan_node> plans(nodes);
+        std::vector<double> costs(bq.size());
+        st = mpdp_host::optimize_units_batch((uint32_t)bq.size(), bq.data(), e.data(), c.data(), s.data(), b.data(),
+                                             cm, X.ws, X.ws_bytes, X.s, plans.data(), costs.data());
+        if (st != MPDP_OK) return st;
+        X.st.launches += 1;
+        uint64_t at = 0;
+        for (size_t g : todo_batch) {
+            out[g] = plan_from_units(*X.P, qs[g], plans.data() + at);
+            at += 2 * qs[g].us.size() - 1;
+        }
+    }
+    for (size_t g : todo_single) {
+        const UnitQuery &Q = qs[g];
+        const uint32_t j = (uint32_t)Q.us.size();
+        mpdp_status st = X.reserve(mpdp_host::units_workspace_bytes(j));
+        if (st != MPDP_OK) return st;
+        std::vector<mpdp_plan_node> plan(2 * j - 1);
+        double cost = 0.0;
+        st = mpdp_host::optimize_units(j, (uint32_t)Q.edges.size(), Q.edges.data(), Q.card.data(), Q.sel.data(),
+                                       Q.bcost.data(), cm, X.ws, X.ws_bytes, X.s, plan.data(), &cost);
+        if (st != MPDP_OK) return st;
+        X.st.launches += 1;
+        out[g] = plan_from_units(*X.P, Q, plan.data());
+    }
+    X.st.ms_exact += now_ms() - t0;
+    return MPDP_OK;
+}
+
+// ---------------------------------------------------------------- GOO
+
+int goo(const Graph &G, Pool &P) {
+    struct Tree {
+        Bits rels;
+        int plan;
+        uint32_t version;
+        std::set<uint32_t> nbrs;
+        bool alive;
+    };
+    std::vector<Tree> T(G.n);
+    uint32_t version = 0;
+    for (uint32_t v = 0; v < G.n; ++v) {
+        T[v] = Tree{G.single(v), P.leaf(v), version++, {}, true};
+        for (uint32_t u : G.adj[v]) T[v].nbrs.insert(u);
+    }
+    using Cand = std::tuple<double, uint32_t, uint32_t, uint32_t, uint32_t>;  // card, i, j, ver i, ver j
+    std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> heap;
+    for (size_t e = 0; e < G.eu.size(); ++e) {
+        const uint32_t i = std::min(G.eu[e], G.ev[e]), j = std::max(G.eu[e], G.ev[e]);
+        heap.push(Cand{G.card_of(T[i].rels | T[j].rels), i, j, T[i].version, T[j].version});
+    }
+    uint32_t left = G.n;
+    int root = G.n == 1 ? T[0].plan : -1;
+    while (left > 1 && !heap.empty()) {
+        const auto [c, i, j, vi, vj] = heap.top();
+        heap.pop();
+        (void)c;
+        if (!T[i].alive || !T[j].alive || T[i].version != vi || T[j].version != vj) continue;
+        Tree &A = T[i];
+        Tree &B = T[j];
+        A.rels = A.rels | B.rels;
+        A.plan = P.join(A.plan, B.plan);
+        A.version = version++;
+        B.alive = false;
+        std::set<uint32_t> nb;
+        for (uint32_t x : A.nbrs) if (x != i && x != j) nb.insert(x);
+        for (uint32_t x : B.nbrs) if (x != i && x != j) nb.insert(x);
+        A.nbrs = nb;
+        B.nbrs.clear();
+        for (uint32_t x : nb) {
+            T[x].nbrs.erase(j);
+            T[x].nbrs.insert(i);
+            const uint32_t lo = std::min(i, x), hi = std::max(i, x);
+            heap.push(Cand{G.card_of(A.rels | T[x].rels), lo, hi, T[lo].version, T[hi].version});
+        }
+        --left;
+        root = A.plan;
+    }
+    return left == 1 ? root : -1;
+}
+
+// ---------------------------------------------------------------- IDP2
+
+mpdp_status idp2(ExactCtx &X, int start, uint32_t k, int &result) {
+    const Graph &G = *X.G;
+    Pool &P = *X.P;
+    struct TNode {
+        int l = -1, r = -1;
+        int unit = -1;
+        // per iteration
+        uint32_t cnt = 0, low = 0;
+        double cost = 0.0, card = 0.0;
+        Bits rels;
+        bool card_done = false;
+    };
+    std::vector<Unit> units;
+    std::vector<TNode> T;
+    // the start plan as a tree whose leaves are units (one per relation)
+    std::function<int(int)> conv = [&](int pid) -> int {
+        const PNode &p = P.nodes[pid];
+        TNode t;
+        if (p.leaf >= 0) {
+            units.push_back(Unit{G.single((uint32_t)p.leaf), pid, (uint32_t)p.leaf});
+            t.unit = (int)units.size() - 1;
+            T.push_back(t);
+            return (int)T.size() - 1;
+        }
+        const int a = conv(p.a);
+        const int b = conv(p.b);
+        t.l = a;
+        t.r = b;
+        T.push_back(t);
+        return (int)T.size() - 1;
+    };
+    const int root = conv(start);
+    while (T[root].unit < 0) {
+        X.st.rounds += 1;
+        // post-order: units below, relation set, cost (re-costing from the children)
+        int best = -1;
+        double best_cost = 0.0;
+        uint32_t best_low = 0;
+        std::vector<std::pair<int, bool>> st{{root, false}};
+        while (!st.empty()) {
+            auto [x, expanded] = st.back();
+            st.pop_back();
+            TNode &t = T[x];
+            if (t.unit >= 0) {
+                const Unit &u = units[t.unit];
+                P.recost(u.plan);
+                t.cnt = 1;
+                t.low = u.low;
+                t.rels = u.rels;
+                t.cost = P.nodes[u.plan].cost;
+                t.card = P.nodes[u.plan].card;
+                continue;
+            }
+            if (!expanded) {
+                st.push_back({x, true});
+                st.push_back({t.r, false});
+                st.push_back({t.l, false});
+                continue;
+            }
+            const TNode &A = T[t.l], &B = T[t.r];
+            t.cnt = A.cnt + B.cnt;
+            t.low = std::min(A.low, B.low);
+            t.rels = A.rels | B.rels;
+            if (!t.card_done) {
+                t.card = G.card_of(t.rels);
+                t.card_done = true;
+            }
+            uint32_t op;
+            bool a_left;
+            combine(G.cm, Side{&A.rels, A.cost, A.card}, Side{&B.rels, B.cost, B.card}, t.card, t.cost, op, a_left);
+            if (t.cnt >= 2 && t.cnt <= k) {
+                // highest cost; ties to the lower lowest relation; first in post-order
+                if (best < 0 || t.cost > best_cost || (t.cost == best_cost && t.low < best_low)) {
+                    best = x;
+                    best_cost = t.cost;
+                    best_low = t.low;
+                }
+            }
+        }
+        // the units below the picked subtree, re-planned exactly
+        std::vector<const Unit *> us;
+        std::vector<int> stack{best};
+        while (!stack.empty()) {
+            const int x = stack.back();
+            stack.pop_back();
+            if (T[x].unit >= 0) us.push_back(&units[T[x].unit]);
+            else { stack.push_back(T[x].r); stack.push_back(T[x].l); }
+        }
+        std::vector<int> plans;
+        mpdp_status s = exact_groups(X, {us}, plans);
+        if (s != MPDP_OK) return s;
+        Bits rels = T[best].rels;
+        const uint32_t low = T[best].low;
+        units.push_back(Unit{std::move(rels), plans[0], low});
+        T[best].unit = (int)units.size() - 1;
+        T[best].l = T[best].r = -1;
+    }
+    result = units[T[root].unit].plan;
+    return MPDP_OK;
+}
+
+// ---------------------------------------------------------------- UnionDP
+
+mpdp_status uniondp(ExactCtx &X, uint32_t k, int &result) {
+    const Graph &G = *X.G;
+    std::vector<Unit> units;
+    for (uint32_t v = 0; v < G.n; ++v) units.push_back(Unit{G.single(v), X.P->leaf(v), v});
+    std::vector<int> where(G.n, -1);
+    while (units.size() > k) {
+        X.st.rounds += 1;
+        std::sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.low < b.low; });
+        for (size_t i = 0; i < units.size(); ++i) units[i].rels.each([&](uint32_t v) { where[v] = (int)i; });
+        std::vector<std::pair<uint32_t, uint32_t>> ue;
+        for (size_t e = 0; e < G.eu.size(); ++e) {
+            const int a = where[G.eu[e]], b = where[G.ev[e]];
+            if (a != b) ue.push_back({(uint32_t)std::min(a, b), (uint32_t)std::max(a, b)});
+        }
+        std::sort(ue.begin(), ue.end());
+        ue.erase(std::unique(ue.begin(), ue.end()), ue.end());
+        std::vector<double> weight(ue.size());
+        for (size_t e = 0; e < ue.size(); ++e) weight[e] = G.card_of(units[ue[e].first].rels | units[ue[e].second].rels);
+        // partition phase: union-find, edges by (size of both parts, weight, edge order)
+        std::vector<uint32_t> parent(units.size()), size(units.size(), 1);
+        for (size_t i = 0; i < units.size(); ++i) parent[i] = (uint32_t)i;
+        auto find = [&](uint32_t x) {
+            while (parent[x] != x) {
+                parent[x] = parent[parent[x]];
+                x = parent[x];
+            }
+            return x;
+        };
+        using Item = std::tuple<uint32_t, double, uint32_t>;
+        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+        for (size_t e = 0; e < ue.size(); ++e) heap.push(Item{2u, weight[e], (uint32_t)e});
+        while (!heap.empty()) {
+            const auto [sz, w, e] = heap.top();
+            heap.pop();
+            const uint32_t ri = find(ue[e].first), rj = find(ue[e].second);
+            if (ri == rj) continue;
+            const uint32_t cur = size[ri] + size[rj];
+            if (cur > k) continue;  // sizes only grow
+            if (cur != sz) {        // re-keyed: the parts have grown
+                heap.push(Item{cur, w, e});
+                continue;
+            }
+            const uint32_t lo = std::min(ri, rj), hi = std::max(ri, rj);
+            parent[hi] = lo;
+            size[lo] += size[hi];
+        }
+        std::map<uint32_t, std::vector<const Unit *>> groups;
+        for (size_t i = 0; i < units.size(); ++i) groups[find((uint32_t)i)].push_back(&units[i]);
+        std::vector<std::vector<const Unit *>> gl;
+        for (auto &kv : groups) gl.push_back(kv.second);
+        std::vector<int> plans;
+        mpdp_status s = exact_groups(X, gl, plans);
+        if (s != MPDP_OK) return s;
+        std::vector<Unit> next;
+        for (size_t g = 0; g < gl.size(); ++g) {
+            Bits r = gl[g][0]->rels;
+            uint32_t low = gl[g][0]->low;
+            for (size_t i = 1; i < gl[g].size(); ++i) {
+                r = r | gl[g][i]->rels;
+                low = std::min(low, gl[g][i]->low);
+            }
+            next.push_back(Unit{std::move(r), plans[g], low});
+        }
+        units = std::move(next);
+    }
+    std::vector<const Unit *> all;
+    for (const Unit &u : units) all.push_back(&u);
+    std::vector<int> plans;
+    mpdp_status s = exact_groups(X, {all}, plans);
+    if (s != MPDP_OK) return s;
+    result = plans[0];
+    return MPDP_OK;
+}
+
+// ---------------------------------------------------------------- validation and output
+
+mpdp_status validate_large(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *card, const double *sel,
+                           mpdp_cost_model cm, Graph &G) {
+    if (n == 0) return MPDP_EINVAL;
+    if (n > kLargeMaxRel) return MPDP_ETOOLARGE;
+    if (cm != MPDP_COST_COUT && cm != MPDP_COST_PGLIKE) return MPDP_EINVAL;
+    if (!card || (m > 0 && (!edges || !sel))) return MPDP_EINVAL;
+    if ((uint64_t)m > (uint64_t)n * (n - 1) / 2) return MPDP_EINVAL;
+    G.n = n;
+    G.words = (n + 63) / 64;
+    G.cm = cm;
+    G.card.assign(card, card + n);
+    for (uint32_t v = 0; v < n; ++v)
+        if (!std::isfinite(card[v]) || !(card[v] >= 1.0)) return MPDP_EINVAL;
+    G.lower.assign(n, {});
+    G.adj.assign(n, {});
+    std::unordered_set<uint64_t> seen;
+    for (uint32_t i = 0; i < m; ++i) {
+        const uint32_t u = edges[i].u, v = edges[i].v;
+        if (u >= n || v >= n || u == v) return MPDP_EINVAL;
+        if (!std::isfinite(sel[i]) || !(sel[i] > 0.0) || !(sel[i] <= 1.0)) return MPDP_EINVAL;
+        const uint32_t a = std::min(u, v), b = std::max(u, v);
+        if (!seen.insert(((uint64_t)a << 32) | b).second) return MPDP_EINVAL;
+        G.eu.push_back(u);
+        G.ev.push_back(v);
+        G.sel.push_back(sel[i]);
+        G.lower[b].push_back({a, sel[i]});
+        G.adj[u].push_back(v);
+        G.adj[v].push_back(u);
+    }
+    for (auto &l : G.lower) std::sort(l.begin(), l.end());
+    std::vector<char> vis(n, 0);
+    std::vector<uint32_t> stack{0};
+    vis[0] = 1;
+    uint32_t reached = 1;
+    while (!stack.empty()) {
+        const uint32_t v = stack.back();
+        stack.pop_back();
+        for (uint32_t u : G.adj[v])
+            if (!vis[u]) { vis[u] = 1; ++reached; stack.push_back(u); }
+    }
+    return reached == n ? MPDP_OK : MPDP_ENOTCONNECTED;
+}
+
+void write_plan(Pool &P, int root, mpdp_large_node *out, uint32_t n) {
+    const Graph &G = *P.G;
+    for (uint32_t v = 0; v < n; ++v)
+        out[v] = mpdp_large_node{-1, -1, v, 1u, MPDP_OP_SCAN, 0u, G.scan_cost(v), G.card[v]};
+    uint32_t next = n;
+    // post-order, left child first
+    std::vector<std::pair<int, int>> st{{root, 0}};
+    std::vector<int> idx;  // results of finished children
+    while (!st.empty()) {
+        auto &[x, stage] = st.back();
+        const PNode &p = P.nodes[x];
+        if (p.leaf >= 0) {
+            idx.push_back(p.leaf);
+            st.pop_back();
+            continue;
+        }
+        if (stage == 0) { stage = 1; st.push_back({p.l, 0}); continue; }
+        if (stage == 1) { stage = 2; st.push_back({p.r, 0}); continue; }
+        const int ri = idx.back(); idx.pop_back();
+        const int li = idx.back(); idx.pop_back();
+        out[next] = mpdp_large_node{li, ri, p.rels.lowest(), p.rels.count(), p.op, 0u, p.cost, p.card};
+        idx.push_back((int)next);
+        ++next;
+        st.pop_back();
+    }
+}
+
+}  // namespace
+
+extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                           const double *cardinalities, const double *selectivities,
+                                           mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
+                                           void *hip_stream, mpdp_large_node *plan_out, double *cost_out,
+                                           mpdp_large_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!plan_out || !cost_out) return MPDP_EINVAL;
+    if (method != MPDP_LARGE_GOO && method != MPDP_LARGE_IDP2 && method != MPDP_LARGE_UNIONDP) return MPDP_EINVAL;
+    if (method != MPDP_LARGE_GOO && (k < 2 || k > kLargeMaxK)) return MPDP_EINVAL;
+    Graph G;
+    mpdp_status st = validate_large(n, m, edges, cardinalities, selectivities, cost_model, G);
+    if (st != MPDP_OK) return st;
+    Pool P;
+    P.G = &G;
+    P.leaf_of.assign(n, -1);
+    P.nodes.reserve(8 * (size_t)n);
+    ExactCtx X;
+    X.G = &G;
+    X.P = &P;
+    X.s = static_cast<hipStream_t>(hip_stream);
+    X.where.assign(n, -1);
+    int root = -1;
+    if (method == MPDP_LARGE_UNIONDP) {
+        st = uniondp(X, k, root);
+    } else {
+        root = goo(G, P);
+        if (root < 0) return MPDP_ENOTCONNECTED;
+        if (method == MPDP_LARGE_IDP2) {
+            const int start = root;
+            st = idp2(X, start, k, root);
+        }
+    }
+    if (st != MPDP_OK) return st;
+    P.recost(root);
+    write_plan(P, root, plan_out, n);
+    *cost_out = P.nodes[root].cost;
+    if (stats_out) {
+        X.st.ms_total = now_ms() - t0;
+        *stats_out = X.st;
+    }
+    return MPDP_OK;
+}

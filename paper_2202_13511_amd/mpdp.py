@@ -24,7 +24,9 @@ MPDP_FLAG_TIMING = 1
 _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
-            "mpdp_optimize_ws", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch"]
+            "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
+            "mpdp_optimize_large"]
+MPDP_LARGE_GOO, MPDP_LARGE_IDP2, MPDP_LARGE_UNIONDP = 0, 1, 2
 
 
 class mpdp_edge(ctypes.Structure):
@@ -53,6 +55,18 @@ class mpdp_batch_stats(ctypes.Structure):
     _fields_ = [("connected_sets", ctypes.c_uint64), ("evaluated_pairs", ctypes.c_uint64),
                 ("ccp_pairs", ctypes.c_uint64), ("ms_total", ctypes.c_double), ("ms_kernel", ctypes.c_double),
                 ("workgroups", ctypes.c_uint32), ("max_n", ctypes.c_uint32)]
+
+
+class mpdp_large_node(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_int32), ("right", ctypes.c_int32), ("rel", ctypes.c_uint32),
+                ("nrels", ctypes.c_uint32), ("op", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("cost", ctypes.c_double), ("card", ctypes.c_double)]
+
+
+class mpdp_large_stats(ctypes.Structure):
+    _fields_ = [("exact_calls", ctypes.c_uint64), ("exact_units", ctypes.c_uint64),
+                ("max_units", ctypes.c_uint32), ("rounds", ctypes.c_uint32), ("launches", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("ms_total", ctypes.c_double), ("ms_exact", ctypes.c_double)]
 
 
 class MpdpError(RuntimeError):
@@ -86,6 +100,11 @@ def load(path: str = LIB_PATH):
     L.mpdp_optimize.restype = ctypes.c_int
     L.mpdp_optimize_ws.argtypes = common + [vp, sz, vp, u32] + outs
     L.mpdp_optimize_ws.restype = ctypes.c_int
+    L.mpdp_optimize_units.argtypes = common[:5] + [f64p, ctypes.c_int, vp, sz, vp, u32] + outs
+    L.mpdp_optimize_units.restype = ctypes.c_int
+    L.mpdp_optimize_large.argtypes = common + [ctypes.c_int, u32, vp, ctypes.POINTER(mpdp_large_node), f64p,
+                                               ctypes.POINTER(mpdp_large_stats)]
+    L.mpdp_optimize_large.restype = ctypes.c_int
     bq = ctypes.POINTER(mpdp_batch_query)
     L.mpdp_batch_workspace_bytes.argtypes = [u32, bq]
     L.mpdp_batch_workspace_bytes.restype = sz
@@ -185,6 +204,52 @@ def mpdp_optimize_ws(query, cost_model: int, ws, stream=None, flags: int = 0) ->
     if st != MPDP_OK:
         raise MpdpError(st, mpdp_status_str(st))
     return _result(n, plan, cost, stats)
+
+
+def mpdp_optimize_units(query, cost_model: int, ws, stream=None, flags: int = 0) -> Result:
+    """mpdp_optimize_ws for a query whose relations are planned intermediate
+    results: ``query.base_cost[v]`` is the cost of relation v's plan."""
+    import torch
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    bc = np.ascontiguousarray(np.asarray(query.base_cost, dtype=np.float64))
+    if stream is None:
+        stream = torch.cuda.current_stream(ws.device)
+    plan = (mpdp_plan_node * max(2 * n - 1, 1))()
+    cost = ctypes.c_double()
+    stats = mpdp_stats()
+    st = load().mpdp_optimize_units(int(n), m, ep, cp, sp, bc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    int(cost_model), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                    ctypes.c_void_p(stream.cuda_stream), int(flags), plan, ctypes.byref(cost),
+                                    ctypes.byref(stats))
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    return _result(n, plan, cost, stats)
+
+
+@dataclass
+class LargeResult:
+    cost: float
+    plan: list            # list of dicts, layout of mpdp_large_node
+    stats: dict
+
+
+def mpdp_optimize_large(query, cost_model: int, method: int, k: int, stream=None) -> LargeResult:
+    """Large-query heuristics (GOO, IDP2, UnionDP) with the exact DP on the
+    GPU as the inner step; the library owns its device workspace."""
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    plan = (mpdp_large_node * max(2 * n - 1, 1))()
+    cost = ctypes.c_double()
+    stats = mpdp_large_stats()
+    sp_handle = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    st = load().mpdp_optimize_large(int(n), m, ep, cp, sp, int(cost_model), int(method), int(k), sp_handle, plan,
+                                    ctypes.byref(cost), ctypes.byref(stats))
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    nodes = [dict(left=p.left, right=p.right, rel=p.rel, nrels=p.nrels, op=p.op, cost=p.cost, card=p.card)
+             for p in plan[: 2 * n - 1]]
+    return LargeResult(cost.value, nodes, {f: getattr(stats, f) for f, _ in mpdp_large_stats._fields_})
 
 
 def memo_index(n: int) -> np.ndarray:
