@@ -25,7 +25,9 @@ _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
             "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
-            "mpdp_optimize_large"]
+            "mpdp_optimize_large", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
+            "mpdp_scorer_load", "mpdp_scorer_forward", "mpdp_scorer_grad", "mpdp_scorer_train_step"]
+SCORER_IN, SCORER_HIDDEN = 32, 256
 MPDP_LARGE_GOO, MPDP_LARGE_IDP2, MPDP_LARGE_UNIONDP = 0, 1, 2
 
 
@@ -105,6 +107,21 @@ def load(path: str = LIB_PATH):
     L.mpdp_optimize_large.argtypes = common + [ctypes.c_int, u32, vp, ctypes.POINTER(mpdp_large_node), f64p,
                                                ctypes.POINTER(mpdp_large_stats)]
     L.mpdp_optimize_large.restype = ctypes.c_int
+    L.mpdp_scorer_param_bytes.argtypes = []
+    L.mpdp_scorer_param_bytes.restype = sz
+    L.mpdp_scorer_work_bytes.argtypes = [u32]
+    L.mpdp_scorer_work_bytes.restype = sz
+    L.mpdp_scorer_layout.argtypes = [ctypes.POINTER(sz)] * 3
+    L.mpdp_scorer_layout.restype = ctypes.c_int
+    f32p = ctypes.POINTER(ctypes.c_float)
+    L.mpdp_scorer_load.argtypes = [vp] + [f32p] * 6 + [vp]
+    L.mpdp_scorer_load.restype = ctypes.c_int
+    L.mpdp_scorer_forward.argtypes = [vp, vp, u32, vp, vp, sz, vp]
+    L.mpdp_scorer_forward.restype = ctypes.c_int
+    L.mpdp_scorer_grad.argtypes = [vp, vp, vp, u32, vp, sz, vp, f32p]
+    L.mpdp_scorer_grad.restype = ctypes.c_int
+    L.mpdp_scorer_train_step.argtypes = [vp, vp, vp, u32, ctypes.c_float, u32, vp, sz, vp, f32p]
+    L.mpdp_scorer_train_step.restype = ctypes.c_int
     bq = ctypes.POINTER(mpdp_batch_query)
     L.mpdp_batch_workspace_bytes.argtypes = [u32, bq]
     L.mpdp_batch_workspace_bytes.restype = sz
@@ -348,3 +365,115 @@ def mpdp_optimize_batch(queries, cost_model: int, ws, stream=None, flags: int = 
                     for p in plans[at: at + k]])
         at += k
     return BatchResult(costs.tolist(), out, lat, {f: getattr(st, f) for f, _ in mpdp_batch_stats._fields_}, start)
+
+
+# ---------------------------------------------------------------- learned scorer (mpdp_scorer.h)
+
+_SCORER_SHAPES = (("w1", (SCORER_IN, SCORER_HIDDEN)), ("b1", (SCORER_HIDDEN,)), ("w2", (SCORER_HIDDEN, SCORER_HIDDEN)),
+                  ("b2", (SCORER_HIDDEN,)), ("w3", (SCORER_HIDDEN,)), ("b3", (1,)))
+
+
+def _check(st):
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev, stream):
+    import torch
+    return ctypes.c_void_p((stream or torch.cuda.current_stream(dev)).cuda_stream)
+
+
+def scorer_params(device="cuda"):
+    """A torch-owned device parameter block."""
+    import torch
+    return torch.zeros(int(load().mpdp_scorer_param_bytes()), dtype=torch.uint8, device=device)
+
+
+def scorer_work(batch: int, device="cuda"):
+    import torch
+    return torch.zeros(max(int(load().mpdp_scorer_work_bytes(int(batch))), 256), dtype=torch.uint8, device=device)
+
+
+def scorer_load(block, weights: dict, stream=None):
+    arrs = [np.ascontiguousarray(np.asarray(weights[k], np.float32).reshape(shape)) for k, shape in _SCORER_SHAPES]
+    f32p = ctypes.POINTER(ctypes.c_float)
+    _check(load().mpdp_scorer_load(_dev(block), *[a.ctypes.data_as(f32p) for a in arrs], _stream(block.device, stream)))
+
+
+def _scorer_region(block, which: str) -> dict:
+    """FP32 master values ('master') or gradients ('grad') as numpy arrays."""
+    import torch
+    o = [ctypes.c_size_t() for _ in range(3)]
+    _check(load().mpdp_scorer_layout(*[ctypes.byref(x) for x in o]))
+    off = o[0].value if which == "master" else o[2].value
+    total = sum(int(np.prod(sh)) for _, sh in _SCORER_SHAPES)
+    torch.cuda.synchronize(block.device)
+    flat = block[off: off + 4 * total].view(torch.float32).cpu().numpy().astype(np.float32)
+    out, at = {}, 0
+    for k, sh in _SCORER_SHAPES:
+        n = int(np.prod(sh))
+        out[k] = flat[at: at + n].reshape(sh)
+        at += n
+    return out
+
+
+def scorer_weights(block) -> dict:
+    return _scorer_region(block, "master")
+
+
+def scorer_grads(block) -> dict:
+    return _scorer_region(block, "grad")
+
+
+def scorer_forward(block, x_bits, work=None, stream=None) -> np.ndarray:
+    """Logits of a batch; x_bits: (B, 32) uint16 bfloat16 bit patterns (numpy or torch int16 on the device)."""
+    import torch
+    x = _to_device_bits(x_bits, block.device)
+    B = x.shape[0]
+    work = work if work is not None else scorer_work(B, block.device)
+    out = torch.empty(B, dtype=torch.float32, device=block.device)
+    _check(load().mpdp_scorer_forward(_dev(block), _dev(x), B, _dev(out), _dev(work), work.numel(),
+                                      _stream(block.device, stream)))
+    return out.cpu().numpy()
+
+
+def _to_device_bits(x_bits, device):
+    import torch
+    if isinstance(x_bits, torch.Tensor):
+        return x_bits.contiguous()
+    a = np.ascontiguousarray(np.asarray(x_bits, np.uint16)).view(np.int16)
+    return torch.from_numpy(a).to(device)
+
+
+def _to_device_f32(y, device):
+    import torch
+    if isinstance(y, torch.Tensor):
+        return y.contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(y, np.float32))).to(device)
+
+
+def scorer_grad(block, x_bits, y, work=None, stream=None) -> float:
+    x = _to_device_bits(x_bits, block.device)
+    yy = _to_device_f32(y, block.device)
+    B = x.shape[0]
+    work = work if work is not None else scorer_work(B, block.device)
+    loss = ctypes.c_float()
+    _check(load().mpdp_scorer_grad(_dev(block), _dev(x), _dev(yy), B, _dev(work), work.numel(),
+                                   _stream(block.device, stream), ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def scorer_train_step(block, x_bits, y, lr: float, step: int, work=None, stream=None, want_loss=True) -> float:
+    x = _to_device_bits(x_bits, block.device)
+    yy = _to_device_f32(y, block.device)
+    B = x.shape[0]
+    work = work if work is not None else scorer_work(B, block.device)
+    loss = ctypes.c_float()
+    _check(load().mpdp_scorer_train_step(_dev(block), _dev(x), _dev(yy), B, float(lr), int(step), _dev(work),
+                                         work.numel(), _stream(block.device, stream),
+                                         ctypes.byref(loss) if want_loss else None))
+    return float(loss.value)
