@@ -239,7 +239,19 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
  * orientation and operator (key: cost, then the left relation set read as a
  * binary number, then HASH before NESTLOOP).  cost_out is that cost.
  */
-typedef enum { MPDP_LARGE_GOO = 0, MPDP_LARGE_IDP2 = 1, MPDP_LARGE_UNIONDP = 2 } mpdp_large_method;
+typedef enum {
+    MPDP_LARGE_GOO = 0,
+    MPDP_LARGE_IDP2 = 1,
+    MPDP_LARGE_UNIONDP = 2,
+    MPDP_LARGE_UNIONDP_LEARNED = 3  /* UnionDP whose partition phase is driven by the scorer of
+                                       mpdp_scorer.h (not part of the paper): parts start as single
+                                       units; each pass scores every union of two adjacent parts with
+                                       at most k units together and joins, by decreasing logit (ties by
+                                       part pair order), every candidate with a positive logit whose
+                                       parts no earlier join of the pass touched; passes repeat until
+                                       none joins.  A round whose first pass joins nothing falls back to
+                                       the paper's order (plain UnionDP). */
+} mpdp_large_method;
 
 /* Plan node of a large query.  Nodes 0..n-1 are the relations in index
  * order; join nodes follow in post-order (left child first); the root is
@@ -265,7 +277,10 @@ typedef struct {
 
 /*
  * Plan a query of 1 <= n <= 4096 relations with `method` and sub-problem
- * bound 2 <= k <= 25 (ignored by GOO).  Inputs follow mpdp_optimize (edges
+ * bound 2 <= k <= 25 (ignored by GOO).  d_scorer is a device parameter
+ * block of mpdp_scorer.h (required by MPDP_LARGE_UNIONDP_LEARNED, ignored
+ * otherwise; the features of a candidate union are listed at
+ * mpdp_large_examples).  Inputs follow mpdp_optimize (edges
  * with distinct unordered endpoint pairs, card >= 1 finite, sel in (0, 1],
  * connected join graph), except for the bound on n.
  *   plan_out   host, caller-allocated, 2n-1 nodes (layout above)
@@ -281,8 +296,38 @@ typedef struct {
 mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
                                 const double *cardinalities, const double *selectivities,
                                 mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
-                                void *hip_stream, mpdp_large_node *plan_out, double *cost_out,
-                                mpdp_large_stats *stats_out);
+                                const void *d_scorer, void *hip_stream, mpdp_large_node *plan_out,
+                                double *cost_out, mpdp_large_stats *stats_out);
+
+/*
+ * Training examples for the scorer from a query of n <= 32 relations whose
+ * optimal plan is known (plan_sets: the relation bitmaps of its nsets
+ * nodes): run learned UnionDP with bound k, driven by d_scorer, or, with
+ * d_scorer NULL, by the teacher that scores a union +1 when it is a node of
+ * the optimal plan and -1 otherwise; emit one row per candidate union of
+ * every pass: MPDP_SCORER_IN BF16 features and a label, 1 iff the union is a
+ * node of the optimal plan.
+ * Features of the union of parts A and B (parts numbered by their lowest
+ * unit, pairs ascending), w = card(A u B), each pair put as (smaller,
+ * larger), computed in binary64 and rounded to binary32 and then to BF16
+ * (nearest even): 0,1 log10 card(A), card(B) / 8; 2 log10 w / 8;
+ * 3 (log10 w - log10 card(A) - log10 card(B)) / 8; 4,5 log10(1 + summed plan
+ * cost of the units of A, B) / 8; 6,7 log2 of their relation counts / 4;
+ * 8,9 their numbers of candidate unions / 8; 10,11 their unit counts / 8;
+ * 12,13 the share of A's (B's) candidates with a smaller weight than w;
+ * 14,15 log10 w - log10 of the smallest weight of a candidate of A (B), / 8;
+ * 16 log2 of the parts / 12; 17 the share of all candidates with a smaller
+ * weight; 18 one; 19..31 zero.
+ * features_out (host, max_examples x MPDP_SCORER_IN), labels_out (host,
+ * max_examples), count_out (host): the number of rows; MPDP_ENOMEM (with
+ * count_out set) when it exceeds max_examples.
+ */
+mpdp_status mpdp_large_examples(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, uint32_t k, const void *d_scorer,
+                                const uint32_t *plan_sets, uint32_t nsets, void *hip_stream,
+                                uint16_t *features_out, float *labels_out, uint32_t max_examples,
+                                uint32_t *count_out);
 
 #ifdef __cplusplus
 }

@@ -38,10 +38,19 @@ H6  UnionDP: the size of a partition counts units; the weight of an edge
     units is planned by the exact step and becomes one unit; the graph of
     units is then processed again until it has at most k units, which the
     exact step plans as a whole.
+
+The learned variant (not in the paper; the scorer of mpdp_scorer.h):
+L1  features of a candidate union of two parts: part_features() below.
+L2  the partition phase joins parts pass by pass in order of the scorer's
+    logits, re-scoring as parts grow: learned_partition() below.
+L3  training label of a union: 1 iff its relation set is a node of the
+    optimal plan (the exact DP's, on queries small enough for it).
+L4  a round in which the learned phase joins nothing uses the paper's order.
 """
 from __future__ import annotations
 
 import heapq
+import math
 import sys
 from dataclasses import dataclass
 
@@ -285,17 +294,32 @@ def idp2(q, k: int, cm: int = COUT, initial=None):
 
 # ------------------------------------------------------------------ UnionDP
 
-def partition(G: Graph, units: list, k: int) -> list[list]:
-    """H6, the partition phase of Alg. 4 over `units` (sorted by lowest
-    relation): groups of units, each connected and of at most k units."""
+def unit_edges(G: Graph, units: list):
+    """Edges between units (sorted by lowest relation): sorted pairs (i, j),
+    i < j, with the number of base edges and the product of their
+    selectivities in edge-list order."""
     where = {}
     for i, (S, _) in enumerate(units):
         T = S
         while T:
             where[lowest(T)] = i
             T &= T - 1
-    uedges = sorted({tuple(sorted((where[a], where[b]))) for a, b in G.edges if where[a] != where[b]})
-    weight = [G.card_of(units[i][0] | units[j][0]) for i, j in uedges]
+    info = {}
+    for (a, b), s in zip(G.edges, G.sel):
+        if where[a] != where[b]:
+            key = tuple(sorted((where[a], where[b])))
+            cnt, prod = info.get(key, (0, 1.0))
+            info[key] = (cnt + 1, prod * s)
+    keys = sorted(info)
+    return keys, [info[k_][0] for k_ in keys], [info[k_][1] for k_ in keys]
+
+
+def partition(G: Graph, units: list, k: int) -> list[list]:
+    """H6, the partition phase of Alg. 4 over `units` (sorted by lowest
+    relation): groups of units, each connected and of at most k units; edges
+    by (current size of both parts, weight, edge order), re-keyed as parts
+    grow."""
+    uedges, _, _ = unit_edges(G, units)
     parent = list(range(len(units)))
     size = [1] * len(units)
 
@@ -305,6 +329,12 @@ def partition(G: Graph, units: list, k: int) -> list[list]:
             x = parent[x]
         return x
 
+    def union(ri, rj):
+        lo, hi = min(ri, rj), max(ri, rj)
+        parent[hi] = lo
+        size[lo] += size[hi]
+
+    weight = [G.card_of(units[i][0] | units[j][0]) for i, j in uedges]
     heap = [(2, weight[e], e) for e in range(len(uedges))]
     heapq.heapify(heap)
     while heap:
@@ -319,24 +349,174 @@ def partition(G: Graph, units: list, k: int) -> list[list]:
         if cur != s:
             heapq.heappush(heap, (cur, w, e))  # re-keyed: the partitions have grown
             continue
-        lo, hi = min(ri, rj), max(ri, rj)
-        parent[hi] = lo
-        size[lo] += size[hi]
+        union(ri, rj)
     groups = {}
     for i in range(len(units)):
         groups.setdefault(find(i), []).append(units[i])
     return [groups[r] for r in sorted(groups)]
 
 
-def uniondp(q, k: int, cm: int = COUT):
-    """Section 4.2, Alg. 4 (H6)."""
+FEATURES = 32
+
+
+def part_features(G: Graph, units: list, parts: list, pairs: list, cm: int, cache=None) -> np.ndarray:
+    """L1: features of candidate unions of two parts (parts are lists of unit
+    indices; pairs (a, b), a < b, index parts), float64, then rounded to
+    float32 and to bfloat16 (bit patterns).  For parts A, B with weight
+    w = card(A u B), each pair put as (smaller, larger):
+      0,1  log10 card(A), card(B)                 / 8
+      2    log10 w                                 / 8
+      3    (log10 w - log10 card(A) - log10 card(B)) / 8
+      4,5  log10(1 + summed plan cost of the units of A, of B) / 8
+      6,7  log2 of the relations of A, B          / 4
+      8,9  candidate unions of A, B               / 8
+      10,11 units of A, B                         / 8
+      12,13 share of A's (B's) candidates with a smaller weight than w
+      14,15 log10 w - log10 of the smallest weight of a candidate of A (B), / 8
+      16   log2 of the parts                       / 12
+      17   share of all candidates with a smaller weight than w
+      18   1
+    the rest 0."""
+    from oracle import mlp
+    rels = []
+    for p in parts:
+        S = 0
+        for u in p:
+            S |= units[u][0]
+        rels.append(S)
+    card = [G.card_of(S) for S in rels]
+    ucost = [recost(G, pl, cm, cache).cost for _, pl in units]
+    cost = []
+    for p in parts:
+        c = 0.0
+        for u in p:
+            c = c + ucost[u]
+        cost.append(c)
+    w = [G.card_of(rels[a] | rels[b]) for a, b in pairs]
+    inc = {}
+    for e, (a, b) in enumerate(pairs):
+        inc.setdefault(a, []).append(w[e])
+        inc.setdefault(b, []).append(w[e])
+    F = np.zeros((len(pairs), FEATURES), np.float64)
+    for e, (a, b) in enumerate(pairs):
+        lw = math.log10(w[e])
+        la, lb = math.log10(card[a]), math.log10(card[b])
+        pa, pb = math.log10(1.0 + cost[a]), math.log10(1.0 + cost[b])
+        na, nb = math.log2(bin(rels[a]).count("1")), math.log2(bin(rels[b]).count("1"))
+        da, db = len(inc[a]), len(inc[b])
+        ua, ub = len(parts[a]), len(parts[b])
+        ra = sum(1 for x in inc[a] if x < w[e]) / da
+        rb = sum(1 for x in inc[b] if x < w[e]) / db
+        ma = lw - math.log10(min(inc[a]))
+        mb = lw - math.log10(min(inc[b]))
+        g = sum(1 for x in w if x < w[e]) / len(w)
+        F[e, 0], F[e, 1] = min(la, lb) / 8, max(la, lb) / 8
+        F[e, 2] = lw / 8
+        F[e, 3] = (lw - la - lb) / 8
+        F[e, 4], F[e, 5] = min(pa, pb) / 8, max(pa, pb) / 8
+        F[e, 6], F[e, 7] = min(na, nb) / 4, max(na, nb) / 4
+        F[e, 8], F[e, 9] = min(da, db) / 8, max(da, db) / 8
+        F[e, 10], F[e, 11] = min(ua, ub) / 8, max(ua, ub) / 8
+        F[e, 12], F[e, 13] = min(ra, rb), max(ra, rb)
+        F[e, 14], F[e, 15] = min(ma, mb) / 8, max(ma, mb) / 8
+        F[e, 16] = math.log2(len(parts)) / 12
+        F[e, 17] = g
+        F[e, 18] = 1.0
+    return mlp.bf16_bits(F)
+
+
+ONE_PER_PASS = True
+
+
+def learned_partition(G: Graph, units: list, k: int, cm: int, score, cache=None, examples=None, plan_sets=None,
+                      one_per_pass=ONE_PER_PASS):
+    """L2: the learned partition phase over `units` (sorted by lowest
+    relation).  Parts start as single units.  Each pass scores every union
+    of two adjacent parts with at most k units together (pairs of part
+    indices ascending, parts numbered by their lowest unit), then joins, by
+    decreasing score (ties by pair order), every candidate with a positive
+    score whose two parts no earlier join of the pass has touched; passes
+    repeat until none joins.  Returns the groups, or None when the first
+    pass joins nothing (the caller then uses the paper's order, L4).  With
+    `examples`, every pass appends (features, labels) (L3)."""
+    where = {}
+    for i, (S, _) in enumerate(units):
+        T = S
+        while T:
+            where[lowest(T)] = i
+            T &= T - 1
+    uedges = sorted({tuple(sorted((where[a], where[b]))) for a, b in G.edges if where[a] != where[b]})
+    parts = [[i] for i in range(len(units))]
+    owner = list(range(len(units)))
+    joined = False
+    while True:
+        pairs = sorted({tuple(sorted((owner[i], owner[j]))) for i, j in uedges
+                        if owner[i] != owner[j] and len(parts[owner[i]]) + len(parts[owner[j]]) <= k})
+        if not pairs:
+            break
+        X = part_features(G, units, parts, pairs, cm, cache)
+        if examples is not None:
+            rel = []
+            for p in parts:
+                S = 0
+                for u in p:
+                    S |= units[u][0]
+                rel.append(S)
+            examples.append((X, np.array([1.0 if (rel[a] | rel[b]) in plan_sets else 0.0 for a, b in pairs])))
+        s = score(X)
+        touched = set()
+        did = False
+        for e in sorted(range(len(pairs)), key=lambda e: (-s[e], e)):
+            if not s[e] > 0:
+                break
+            a, b = pairs[e]
+            if a in touched or b in touched:
+                continue
+            parts[a] = parts[a] + parts[b]
+            parts[b] = []
+            touched.add(a)
+            touched.add(b)
+            did = True
+            if one_per_pass:
+                break
+        if not did:
+            break
+        joined = True
+        parts = [sorted(p) for p in sorted((p for p in parts if p), key=min)]
+        for pi, p in enumerate(parts):
+            for u in p:
+                owner[u] = pi
+    if not joined:
+        return None
+    return [[units[u] for u in p] for p in parts]
+
+
+def uniondp(q, k: int, cm: int = COUT, scorer=None, examples=None, plan_sets=None, teacher=False):
+    """Section 4.2, Alg. 4 (H6).  With `scorer` (features -> one score per
+    candidate union), the learned partition phase (L2), falling back to the
+    paper's order for a round in which it joins nothing (L4).  teacher=True
+    scores a candidate +1 if its union is one of `plan_sets` (the nodes of an
+    optimal plan) and -1 otherwise.  With `examples`, the learned passes
+    append (features, labels) (L3)."""
     G = Graph(q)
     cache = {}
     units = [(1 << v, ("leaf", v)) for v in range(q.n)]
+    if teacher:
+        last = []
+        buf = examples if examples is not None else []
+
+        def scorer(X, buf=buf):
+            return buf[-1][1] * 2.0 - 1.0
+        examples = buf
     while len(units) > k:
         units = sorted(units, key=lambda u: lowest(u[0]))
+        groups = None
+        if scorer is not None:
+            groups = learned_partition(G, units, k, cm, scorer, cache, examples, plan_sets)
+        if groups is None:
+            groups = partition(G, units, k)
         nxt = []
-        for members in partition(G, units, k):
+        for members in groups:
             S = 0
             for m_ in members:
                 S |= m_[0]

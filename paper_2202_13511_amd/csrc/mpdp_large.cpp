@@ -20,12 +20,14 @@
 
 #include "mpdp.h"
 #include "mpdp_host_internal.h"
+#include "mpdp_scorer.h"
 
 namespace {
 
 constexpr uint32_t kLargeMaxRel = 4096;
 constexpr uint32_t kLargeMaxK = 25;
 constexpr uint32_t kBatchUnits = 20;  // parts of at most this many units go through the batched kernel
+constexpr bool kOnePerPass = true;    // learned partition: one join (the best-scored) per pass
 
 double now_ms() {
     using namespace std::chrono;
@@ -220,9 +222,19 @@ struct ExactCtx {
     size_t ws_bytes = 0;
     std::vector<int> where;  // relation -> local unit index, -1 outside
     mpdp_large_stats st{};
+    // learned union order: scorer parameters (device) and scratch
+    const void *scorer = nullptr;
+    void *sc_buf = nullptr;
+    size_t sc_bytes = 0;
+    // training examples: optimal plan's relation sets and the output
+    const std::unordered_set<uint32_t> *plan_sets = nullptr;  // teacher labels (n <= 32)
+    bool teacher = false;                                     // score = +1 for plan nodes, -1 otherwise
+    std::vector<uint16_t> *ex_x = nullptr;
+    std::vector<float> *ex_y = nullptr;
 
     ~ExactCtx() {
         if (ws) (void)hipFree(ws);
+        if (sc_buf) (void)hipFree(sc_buf);
     }
     mpdp_status reserve(size_t bytes) {
         if (bytes <= ws_bytes) return MPDP_OK;
@@ -505,7 +517,212 @@ mpdp_status idp2(ExactCtx &X, int start, uint32_t k, int &result) {
     return MPDP_OK;
 }
 
+// ---------------------------------------------------------------- learned union order
+
+uint16_t bf16_bits(double x) {
+    const float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Features of candidate unions of two parts (parts: unit indices; pairs
+// (a, b), a < b), float64, rounded to float32 and then to bfloat16.  For
+// parts A, B with weight w = card(A u B), every pair put as (smaller, larger):
+//  0,1 log10 card(A), card(B) / 8;  2 log10 w / 8;
+//  3 (log10 w - log10 card(A) - log10 card(B)) / 8;
+//  4,5 log10(1 + summed plan cost of the units of A, B) / 8;
+//  6,7 log2 relations of A, B / 4;  8,9 candidate unions of A, B / 8;
+//  10,11 units of A, B / 8;  12,13 share of A's (B's) candidates with a smaller weight;
+//  14,15 log10 w - log10 of the smallest weight at A (B), / 8;
+//  16 log2 parts / 12;  17 share of all candidates with a smaller weight;  18 one.
+void part_features(const Graph &G, Pool &P, const std::vector<Unit> &units,
+                   const std::vector<std::vector<uint32_t>> &parts,
+                   const std::vector<std::pair<uint32_t, uint32_t>> &pairs, std::vector<Bits> &rels,
+                   std::vector<uint16_t> &X) {
+    const size_t np = parts.size(), ne = pairs.size();
+    rels.assign(np, Bits(G.words));
+    std::vector<double> card(np), cost(np), nrel(np), ucost(units.size());
+    for (size_t u = 0; u < units.size(); ++u) {
+        P.recost(units[u].plan);
+        ucost[u] = P.nodes[units[u].plan].cost;
+    }
+    for (size_t a = 0; a < np; ++a) {
+        double c = 0.0;
+        for (uint32_t u : parts[a]) {
+            rels[a] = rels[a] | units[u].rels;
+            c = c + ucost[u];
+        }
+        cost[a] = c;
+        card[a] = G.card_of(rels[a]);
+        nrel[a] = (double)rels[a].count();
+    }
+    std::vector<double> w(ne);
+    std::vector<std::vector<double>> inc(np);
+    for (size_t e = 0; e < ne; ++e) {
+        w[e] = G.card_of(rels[pairs[e].first] | rels[pairs[e].second]);
+        inc[pairs[e].first].push_back(w[e]);
+        inc[pairs[e].second].push_back(w[e]);
+    }
+    X.assign(ne * MPDP_SCORER_IN, 0);
+    for (size_t e = 0; e < ne; ++e) {
+        const uint32_t a = pairs[e].first, b = pairs[e].second;
+        double f[MPDP_SCORER_IN] = {0.0};
+        const double lw = std::log10(w[e]);
+        const double la = std::log10(card[a]), lb = std::log10(card[b]);
+        const double pa = std::log10(1.0 + cost[a]), pb = std::log10(1.0 + cost[b]);
+        const double na = std::log2(nrel[a]), nb = std::log2(nrel[b]);
+        const double da = (double)inc[a].size(), db = (double)inc[b].size();
+        const double ua = (double)parts[a].size(), ub = (double)parts[b].size();
+        double ca = 0.0, cb = 0.0, cg = 0.0;
+        for (double x : inc[a]) ca += x < w[e] ? 1.0 : 0.0;
+        for (double x : inc[b]) cb += x < w[e] ? 1.0 : 0.0;
+        for (double x : w) cg += x < w[e] ? 1.0 : 0.0;
+        const double ra = ca / da, rb = cb / db;
+        const double ma = lw - std::log10(*std::min_element(inc[a].begin(), inc[a].end()));
+        const double mb = lw - std::log10(*std::min_element(inc[b].begin(), inc[b].end()));
+        f[0] = std::min(la, lb) / 8; f[1] = std::max(la, lb) / 8;
+        f[2] = lw / 8;
+        f[3] = (lw - la - lb) / 8;
+        f[4] = std::min(pa, pb) / 8; f[5] = std::max(pa, pb) / 8;
+        f[6] = std::min(na, nb) / 4; f[7] = std::max(na, nb) / 4;
+        f[8] = std::min(da, db) / 8; f[9] = std::max(da, db) / 8;
+        f[10] = std::min(ua, ub) / 8; f[11] = std::max(ua, ub) / 8;
+        f[12] = std::min(ra, rb); f[13] = std::max(ra, rb);
+        f[14] = std::min(ma, mb) / 8; f[15] = std::max(ma, mb) / 8;
+        f[16] = std::log2((double)np) / 12;
+        f[17] = cg / (double)ne;
+        f[18] = 1.0;
+        for (int t = 0; t < MPDP_SCORER_IN; ++t) X[e * MPDP_SCORER_IN + t] = bf16_bits(f[t]);
+    }
+}
+
+// Logits of the rows of X from the scorer on the GPU.
+mpdp_status score_rows(ExactCtx &X, const std::vector<uint16_t> &feat, std::vector<float> &logit) {
+    const uint32_t rows = (uint32_t)(feat.size() / MPDP_SCORER_IN);
+    logit.assign(rows, 0.f);
+    if (rows == 0) return MPDP_OK;
+    const size_t xb = (2 * feat.size() + 255) & ~(size_t)255, lb = (4 * (size_t)rows + 255) & ~(size_t)255;
+    const size_t wb = mpdp_scorer_work_bytes(rows);
+    const size_t need = xb + lb + wb;
+    if (need > X.sc_bytes) {
+        if (X.sc_buf && hipFree(X.sc_buf) != hipSuccess) return MPDP_EDEVICE;
+        X.sc_buf = nullptr;
+        X.sc_bytes = 0;
+        if (hipMalloc(&X.sc_buf, need) != hipSuccess || !X.sc_buf) {
+            (void)hipGetLastError();
+            X.sc_buf = nullptr;
+            return MPDP_ENOMEM;
+        }
+        X.sc_bytes = need;
+    }
+    char *b = static_cast<char *>(X.sc_buf);
+    if (hipMemcpyAsync(b, feat.data(), 2 * feat.size(), hipMemcpyHostToDevice, X.s) != hipSuccess) return MPDP_EDEVICE;
+    mpdp_status st = mpdp_scorer_forward(X.scorer, reinterpret_cast<const uint16_t *>(b), rows,
+                                         reinterpret_cast<float *>(b + xb), b + xb + lb, wb, X.s);
+    if (st != MPDP_OK) return st;
+    if (hipMemcpyAsync(logit.data(), b + xb, 4 * (size_t)rows, hipMemcpyDeviceToHost, X.s) != hipSuccess)
+        return MPDP_EDEVICE;
+    if (hipStreamSynchronize(X.s) != hipSuccess) return MPDP_EDEVICE;
+    return MPDP_OK;
+}
+
 // ---------------------------------------------------------------- UnionDP
+
+// The learned partition phase over `units` (sorted by lowest relation):
+// parts start as single units; each pass scores every union of two adjacent
+// parts with at most k units together (part pairs ascending, parts numbered
+// by their lowest unit) and joins, by decreasing score (ties by pair
+// order), every candidate with a positive score whose parts no earlier join
+// of the pass touched; passes repeat until none joins.  `have` is false when
+// the first pass joins nothing (the paper's order is used then).
+mpdp_status learned_partition(ExactCtx &X, const std::vector<Unit> &units, const std::vector<int> &where, uint32_t k,
+                              std::vector<std::vector<const Unit *>> &groups, bool &have) {
+    const Graph &G = *X.G;
+    std::vector<std::pair<uint32_t, uint32_t>> ue;
+    for (size_t e = 0; e < G.eu.size(); ++e) {
+        const int a = where[G.eu[e]], b = where[G.ev[e]];
+        if (a != b) ue.push_back({(uint32_t)std::min(a, b), (uint32_t)std::max(a, b)});
+    }
+    std::sort(ue.begin(), ue.end());
+    ue.erase(std::unique(ue.begin(), ue.end()), ue.end());
+    std::vector<std::vector<uint32_t>> parts(units.size());
+    std::vector<uint32_t> owner(units.size());
+    for (uint32_t i = 0; i < units.size(); ++i) { parts[i] = {i}; owner[i] = i; }
+    bool joined = false;
+    std::vector<Bits> rels;
+    std::vector<uint16_t> feat;
+    std::vector<float> score;
+    for (;;) {
+        std::vector<std::pair<uint32_t, uint32_t>> pairs;
+        for (const auto &e : ue) {
+            const uint32_t a = owner[e.first], b = owner[e.second];
+            if (a != b && parts[a].size() + parts[b].size() <= k) pairs.push_back({std::min(a, b), std::max(a, b)});
+        }
+        std::sort(pairs.begin(), pairs.end());
+        pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+        if (pairs.empty()) break;
+        part_features(G, *X.P, units, parts, pairs, rels, feat);
+        std::vector<float> label;
+        if (X.plan_sets) {
+            for (const auto &pr : pairs) {
+                const Bits S = rels[pr.first] | rels[pr.second];
+                label.push_back(X.plan_sets->count((uint32_t)S.w[0]) ? 1.f : 0.f);
+            }
+        }
+        if (X.ex_x) {
+            X.ex_x->insert(X.ex_x->end(), feat.begin(), feat.end());
+            X.ex_y->insert(X.ex_y->end(), label.begin(), label.end());
+        }
+        if (X.teacher) {
+            score.resize(pairs.size());
+            for (size_t e = 0; e < pairs.size(); ++e) score[e] = label[e] * 2.f - 1.f;
+        } else {
+            const double t0 = now_ms();
+            mpdp_status st = score_rows(X, feat, score);
+            if (st != MPDP_OK) return st;
+            X.st.ms_exact += now_ms() - t0;
+        }
+        std::vector<uint32_t> order(pairs.size());
+        for (size_t e = 0; e < pairs.size(); ++e) order[e] = (uint32_t)e;
+        std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+            return score[x] != score[y] ? score[x] > score[y] : x < y;
+        });
+        std::vector<char> touched(parts.size(), 0);
+        bool did = false;
+        for (uint32_t e : order) {
+            if (!(score[e] > 0.f)) break;
+            const uint32_t a = pairs[e].first, b = pairs[e].second;
+            if (touched[a] || touched[b]) continue;
+            parts[a].insert(parts[a].end(), parts[b].begin(), parts[b].end());
+            parts[b].clear();
+            touched[a] = touched[b] = 1;
+            did = true;
+            if (kOnePerPass) break;
+        }
+        if (!did) break;
+        joined = true;
+        std::vector<std::vector<uint32_t>> live;
+        for (auto &p : parts)
+            if (!p.empty()) { std::sort(p.begin(), p.end()); live.push_back(std::move(p)); }
+        std::sort(live.begin(), live.end(), [](const std::vector<uint32_t> &x, const std::vector<uint32_t> &y) {
+            return x[0] < y[0];
+        });
+        parts = std::move(live);
+        for (uint32_t pi = 0; pi < parts.size(); ++pi)
+            for (uint32_t u : parts[pi]) owner[u] = pi;
+    }
+    have = joined;
+    groups.clear();
+    if (!joined) return MPDP_OK;
+    for (const auto &p : parts) {
+        std::vector<const Unit *> g;
+        for (uint32_t u : p) g.push_back(&units[u]);
+        groups.push_back(std::move(g));
+    }
+    return MPDP_OK;
+}
 
 mpdp_status uniondp(ExactCtx &X, uint32_t k, int &result) {
     const Graph &G = *X.G;
@@ -516,47 +733,55 @@ mpdp_status uniondp(ExactCtx &X, uint32_t k, int &result) {
         X.st.rounds += 1;
         std::sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.low < b.low; });
         for (size_t i = 0; i < units.size(); ++i) units[i].rels.each([&](uint32_t v) { where[v] = (int)i; });
-        std::vector<std::pair<uint32_t, uint32_t>> ue;
-        for (size_t e = 0; e < G.eu.size(); ++e) {
-            const int a = where[G.eu[e]], b = where[G.ev[e]];
-            if (a != b) ue.push_back({(uint32_t)std::min(a, b), (uint32_t)std::max(a, b)});
-        }
-        std::sort(ue.begin(), ue.end());
-        ue.erase(std::unique(ue.begin(), ue.end()), ue.end());
-        std::vector<double> weight(ue.size());
-        for (size_t e = 0; e < ue.size(); ++e) weight[e] = G.card_of(units[ue[e].first].rels | units[ue[e].second].rels);
-        // partition phase: union-find, edges by (size of both parts, weight, edge order)
-        std::vector<uint32_t> parent(units.size()), size(units.size(), 1);
-        for (size_t i = 0; i < units.size(); ++i) parent[i] = (uint32_t)i;
-        auto find = [&](uint32_t x) {
-            while (parent[x] != x) {
-                parent[x] = parent[parent[x]];
-                x = parent[x];
-            }
-            return x;
-        };
-        using Item = std::tuple<uint32_t, double, uint32_t>;
-        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-        for (size_t e = 0; e < ue.size(); ++e) heap.push(Item{2u, weight[e], (uint32_t)e});
-        while (!heap.empty()) {
-            const auto [sz, w, e] = heap.top();
-            heap.pop();
-            const uint32_t ri = find(ue[e].first), rj = find(ue[e].second);
-            if (ri == rj) continue;
-            const uint32_t cur = size[ri] + size[rj];
-            if (cur > k) continue;  // sizes only grow
-            if (cur != sz) {        // re-keyed: the parts have grown
-                heap.push(Item{cur, w, e});
-                continue;
-            }
-            const uint32_t lo = std::min(ri, rj), hi = std::max(ri, rj);
-            parent[hi] = lo;
-            size[lo] += size[hi];
-        }
-        std::map<uint32_t, std::vector<const Unit *>> groups;
-        for (size_t i = 0; i < units.size(); ++i) groups[find((uint32_t)i)].push_back(&units[i]);
         std::vector<std::vector<const Unit *>> gl;
-        for (auto &kv : groups) gl.push_back(kv.second);
+        bool have = false;
+        if (X.scorer || X.teacher) {
+            mpdp_status ls = learned_partition(X, units, where, k, gl, have);
+            if (ls != MPDP_OK) return ls;
+        }
+        if (!have) {  // the paper's partition phase
+            std::vector<std::pair<uint32_t, uint32_t>> ue;
+            for (size_t e = 0; e < G.eu.size(); ++e) {
+                const int a = where[G.eu[e]], b = where[G.ev[e]];
+                if (a != b) ue.push_back({(uint32_t)std::min(a, b), (uint32_t)std::max(a, b)});
+            }
+            std::sort(ue.begin(), ue.end());
+            ue.erase(std::unique(ue.begin(), ue.end()), ue.end());
+            std::vector<double> weight(ue.size());
+            for (size_t e = 0; e < ue.size(); ++e)
+                weight[e] = G.card_of(units[ue[e].first].rels | units[ue[e].second].rels);
+            std::vector<uint32_t> parent(units.size()), size(units.size(), 1);
+            for (size_t i = 0; i < units.size(); ++i) parent[i] = (uint32_t)i;
+            auto find = [&](uint32_t x) {
+                while (parent[x] != x) {
+                    parent[x] = parent[parent[x]];
+                    x = parent[x];
+                }
+                return x;
+            };
+            // edges by (size of both parts, weight, edge order), re-keyed as parts grow
+            using Item = std::tuple<uint32_t, double, uint32_t>;
+            std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+            for (size_t e = 0; e < ue.size(); ++e) heap.push(Item{2u, weight[e], (uint32_t)e});
+            while (!heap.empty()) {
+                const auto [sz, w, e] = heap.top();
+                heap.pop();
+                const uint32_t ri = find(ue[e].first), rj = find(ue[e].second);
+                if (ri == rj) continue;
+                const uint32_t cur = size[ri] + size[rj];
+                if (cur > k) continue;  // sizes only grow
+                if (cur != sz) {        // re-keyed: the parts have grown
+                    heap.push(Item{cur, w, e});
+                    continue;
+                }
+                const uint32_t lo = std::min(ri, rj), hi = std::max(ri, rj);
+                parent[hi] = lo;
+                size[lo] += size[hi];
+            }
+            std::map<uint32_t, std::vector<const Unit *>> groups;
+            for (size_t i = 0; i < units.size(); ++i) groups[find((uint32_t)i)].push_back(&units[i]);
+            for (auto &kv : groups) gl.push_back(kv.second);
+        }
         std::vector<int> plans;
         mpdp_status s = exact_groups(X, gl, plans);
         if (s != MPDP_OK) return s;
@@ -658,11 +883,14 @@ void write_plan(Pool &P, int root, mpdp_large_node *out, uint32_t n) {
 extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
                                            const double *cardinalities, const double *selectivities,
                                            mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
-                                           void *hip_stream, mpdp_large_node *plan_out, double *cost_out,
-                                           mpdp_large_stats *stats_out) {
+                                           const void *d_scorer, void *hip_stream, mpdp_large_node *plan_out,
+                                           double *cost_out, mpdp_large_stats *stats_out) {
     const double t0 = now_ms();
     if (!plan_out || !cost_out) return MPDP_EINVAL;
-    if (method != MPDP_LARGE_GOO && method != MPDP_LARGE_IDP2 && method != MPDP_LARGE_UNIONDP) return MPDP_EINVAL;
+    if (method != MPDP_LARGE_GOO && method != MPDP_LARGE_IDP2 && method != MPDP_LARGE_UNIONDP &&
+        method != MPDP_LARGE_UNIONDP_LEARNED)
+        return MPDP_EINVAL;
+    if (method == MPDP_LARGE_UNIONDP_LEARNED && !d_scorer) return MPDP_EINVAL;
     if (method != MPDP_LARGE_GOO && (k < 2 || k > kLargeMaxK)) return MPDP_EINVAL;
     Graph G;
     mpdp_status st = validate_large(n, m, edges, cardinalities, selectivities, cost_model, G);
@@ -676,8 +904,9 @@ extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_ed
     X.P = &P;
     X.s = static_cast<hipStream_t>(hip_stream);
     X.where.assign(n, -1);
+    if (method == MPDP_LARGE_UNIONDP_LEARNED) X.scorer = d_scorer;
     int root = -1;
-    if (method == MPDP_LARGE_UNIONDP) {
+    if (method == MPDP_LARGE_UNIONDP || method == MPDP_LARGE_UNIONDP_LEARNED) {
         st = uniondp(X, k, root);
     } else {
         root = goo(G, P);
@@ -695,5 +924,43 @@ extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_ed
         X.st.ms_total = now_ms() - t0;
         *stats_out = X.st;
     }
+    return MPDP_OK;
+}
+
+extern "C" mpdp_status mpdp_large_examples(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,
+                                          const double *selectivities, mpdp_cost_model cost_model, uint32_t k,
+                                          const void *d_scorer, const uint32_t *plan_sets, uint32_t nsets,
+                                          void *hip_stream, uint16_t *features_out, float *labels_out,
+                                          uint32_t max_examples, uint32_t *count_out) {
+    if (!plan_sets || !count_out || (max_examples > 0 && (!features_out || !labels_out))) return MPDP_EINVAL;
+    if (n > 32) return MPDP_ETOOLARGE;
+    if (k < 2 || k > kLargeMaxK) return MPDP_EINVAL;
+    Graph G;
+    mpdp_status st = validate_large(n, m, edges, cardinalities, selectivities, cost_model, G);
+    if (st != MPDP_OK) return st;
+    std::unordered_set<uint32_t> sets(plan_sets, plan_sets + nsets);
+    std::vector<uint16_t> ex;
+    std::vector<float> ey;
+    Pool P;
+    P.G = &G;
+    P.leaf_of.assign(n, -1);
+    ExactCtx X;
+    X.G = &G;
+    X.P = &P;
+    X.s = static_cast<hipStream_t>(hip_stream);
+    X.where.assign(n, -1);
+    X.scorer = d_scorer;
+    X.teacher = d_scorer == nullptr;
+    X.plan_sets = &sets;
+    X.ex_x = &ex;
+    X.ex_y = &ey;
+    int root = -1;
+    st = uniondp(X, k, root);
+    if (st != MPDP_OK) return st;
+    const uint32_t count = (uint32_t)ey.size();
+    *count_out = count;
+    if (count > max_examples) return MPDP_ENOMEM;
+    std::memcpy(features_out, ex.data(), 2 * ex.size());
+    std::memcpy(labels_out, ey.data(), 4 * ey.size());
     return MPDP_OK;
 }

@@ -25,10 +25,10 @@ _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
             "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
-            "mpdp_optimize_large", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
+            "mpdp_optimize_large", "mpdp_large_examples", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
             "mpdp_scorer_load", "mpdp_scorer_forward", "mpdp_scorer_grad", "mpdp_scorer_train_step"]
 SCORER_IN, SCORER_HIDDEN = 32, 256
-MPDP_LARGE_GOO, MPDP_LARGE_IDP2, MPDP_LARGE_UNIONDP = 0, 1, 2
+MPDP_LARGE_GOO, MPDP_LARGE_IDP2, MPDP_LARGE_UNIONDP, MPDP_LARGE_UNIONDP_LEARNED = 0, 1, 2, 3
 
 
 class mpdp_edge(ctypes.Structure):
@@ -87,6 +87,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2202_13511_amd.build.build()")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one this library links.  Loading torch first makes both use that one
+    # runtime; the other order leaves torch unable to initialise the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     u32, sz, vp = ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p
     f64p = ctypes.POINTER(ctypes.c_double)
@@ -104,8 +111,11 @@ def load(path: str = LIB_PATH):
     L.mpdp_optimize_ws.restype = ctypes.c_int
     L.mpdp_optimize_units.argtypes = common[:5] + [f64p, ctypes.c_int, vp, sz, vp, u32] + outs
     L.mpdp_optimize_units.restype = ctypes.c_int
-    L.mpdp_optimize_large.argtypes = common + [ctypes.c_int, u32, vp, ctypes.POINTER(mpdp_large_node), f64p,
+    L.mpdp_optimize_large.argtypes = common + [ctypes.c_int, u32, vp, vp, ctypes.POINTER(mpdp_large_node), f64p,
                                                ctypes.POINTER(mpdp_large_stats)]
+    L.mpdp_large_examples.argtypes = common + [u32, vp, ctypes.POINTER(ctypes.c_uint32), u32, vp, vp,
+                                               ctypes.POINTER(ctypes.c_float), u32, ctypes.POINTER(ctypes.c_uint32)]
+    L.mpdp_large_examples.restype = ctypes.c_int
     L.mpdp_optimize_large.restype = ctypes.c_int
     L.mpdp_scorer_param_bytes.argtypes = []
     L.mpdp_scorer_param_bytes.restype = sz
@@ -251,22 +261,49 @@ class LargeResult:
     stats: dict
 
 
-def mpdp_optimize_large(query, cost_model: int, method: int, k: int, stream=None) -> LargeResult:
-    """Large-query heuristics (GOO, IDP2, UnionDP) with the exact DP on the
-    GPU as the inner step; the library owns its device workspace."""
+def mpdp_optimize_large(query, cost_model: int, method: int, k: int, scorer=None, stream=None) -> LargeResult:
+    """Large-query heuristics (GOO, IDP2, UnionDP, learned UnionDP) with the
+    exact DP on the GPU as the inner step; the library owns its device
+    workspace.  scorer: a device parameter block (scorer_params())."""
     n, edges, card, sel = _args(query)
     keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
     plan = (mpdp_large_node * max(2 * n - 1, 1))()
     cost = ctypes.c_double()
     stats = mpdp_large_stats()
     sp_handle = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
-    st = load().mpdp_optimize_large(int(n), m, ep, cp, sp, int(cost_model), int(method), int(k), sp_handle, plan,
-                                    ctypes.byref(cost), ctypes.byref(stats))
+    sc = None if scorer is None else ctypes.c_void_p(scorer.data_ptr())
+    st = load().mpdp_optimize_large(int(n), m, ep, cp, sp, int(cost_model), int(method), int(k), sc, sp_handle,
+                                    plan, ctypes.byref(cost), ctypes.byref(stats))
     if st != MPDP_OK:
         raise MpdpError(st, mpdp_status_str(st))
     nodes = [dict(left=p.left, right=p.right, rel=p.rel, nrels=p.nrels, op=p.op, cost=p.cost, card=p.card)
              for p in plan[: 2 * n - 1]]
     return LargeResult(cost.value, nodes, {f: getattr(stats, f) for f, _ in mpdp_large_stats._fields_})
+
+
+def mpdp_large_examples(query, cost_model: int, k: int, plan_sets, scorer=None, stream=None):
+    """(features (rows, 32) uint16 bfloat16 bits, labels (rows,) float32) of
+    UnionDP's candidate unions on a query of n <= 32 relations whose optimal
+    plan has the relation sets `plan_sets`."""
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    sets = np.ascontiguousarray(np.asarray(sorted(plan_sets), np.uint32))
+    sc = None if scorer is None else ctypes.c_void_p(scorer.data_ptr())
+    sp_handle = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    cap = 4096
+    while True:
+        X = np.zeros((cap, SCORER_IN), np.uint16)
+        y = np.zeros(cap, np.float32)
+        cnt = ctypes.c_uint32()
+        st = load().mpdp_large_examples(int(n), m, ep, cp, sp, int(cost_model), int(k), sc,
+                                        sets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), len(sets), sp_handle,
+                                        ctypes.c_void_p(X.ctypes.data), y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        cap, ctypes.byref(cnt))
+        if st == MPDP_ENOMEM and cnt.value > cap:
+            cap = int(cnt.value)
+            continue
+        _check(st)
+        return X[: cnt.value], y[: cnt.value]
 
 
 def memo_index(n: int) -> np.ndarray:
