@@ -246,9 +246,8 @@ typedef enum {
     MPDP_LARGE_UNIONDP_LEARNED = 3  /* UnionDP whose partition phase is driven by the scorer of
                                        mpdp_scorer.h (not part of the paper): parts start as single
                                        units; each pass scores every union of two adjacent parts with
-                                       at most k units together and joins, by decreasing logit (ties by
-                                       part pair order), every candidate with a positive logit whose
-                                       parts no earlier join of the pass touched; passes repeat until
+                                       at most k units together and joins the best-scored one (ties by
+                                       part pair order) if its logit is positive; passes repeat until
                                        none joins.  A round whose first pass joins nothing falls back to
                                        the paper's order (plain UnionDP). */
 } mpdp_large_method;

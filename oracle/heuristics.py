@@ -41,8 +41,8 @@ H6  UnionDP: the size of a partition counts units; the weight of an edge
 
 The learned variant (not in the paper; the scorer of mpdp_scorer.h):
 L1  features of a candidate union of two parts: part_features() below.
-L2  the partition phase joins parts pass by pass in order of the scorer's
-    logits, re-scoring as parts grow: learned_partition() below.
+L2  the partition phase joins parts one at a time, the best-scored union
+    first, re-scoring after every join: learned_partition() below.
 L3  training label of a union: 1 iff its relation set is a node of the
     optimal plan (the exact DP's, on queries small enough for it).
 L4  a round in which the learned phase joins nothing uses the paper's order.
@@ -433,10 +433,11 @@ def learned_partition(G: Graph, units: list, k: int, cm: int, score, cache=None,
     """L2: the learned partition phase over `units` (sorted by lowest
     relation).  Parts start as single units.  Each pass scores every union
     of two adjacent parts with at most k units together (pairs of part
-    indices ascending, parts numbered by their lowest unit), then joins, by
-    decreasing score (ties by pair order), every candidate with a positive
-    score whose two parts no earlier join of the pass has touched; passes
-    repeat until none joins.  Returns the groups, or None when the first
+    indices ascending, parts numbered by their lowest unit), then joins the
+    best-scored candidate (ties by pair order) if its score is positive
+    (one_per_pass=False: every positive candidate, by decreasing score, whose
+    parts no earlier join of the pass touched); passes repeat until none
+    joins.  Returns the groups, or None when the first
     pass joins nothing (the caller then uses the paper's order, L4).  With
     `examples`, every pass appends (features, labels) (L3)."""
     where = {}

@@ -633,9 +633,8 @@ mpdp_status score_rows(ExactCtx &X, const std::vector<uint16_t> &feat, std::vect
 // The learned partition phase over `units` (sorted by lowest relation):
 // parts start as single units; each pass scores every union of two adjacent
 // parts with at most k units together (part pairs ascending, parts numbered
-// by their lowest unit) and joins, by decreasing score (ties by pair
-// order), every candidate with a positive score whose parts no earlier join
-// of the pass touched; passes repeat until none joins.  `have` is false when
+// by their lowest unit) and joins the best-scored candidate (ties by pair
+// order) if its score is positive; passes repeat until none joins.  `have` is false when
 // the first pass joins nothing (the paper's order is used then).
 mpdp_status learned_partition(ExactCtx &X, const std::vector<Unit> &units, const std::vector<int> &where, uint32_t k,
                               std::vector<std::vector<const Unit *>> &groups, bool &have) {
