@@ -114,7 +114,9 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
     const uint64_t list_off = (21 * N + 255) & ~255ull;
     uint32_t *list = reinterpret_cast<uint32_t *>(slot + list_off);
-    const uint32_t cap = L.binom[maxn * 33 + maxn / 2];  // sets of the widest level
+    // sets of the widest level; read from global memory: the LDS copy of the
+    // table is complete only after the first barrier below
+    const uint32_t cap = binom_g[maxn * 33 + maxn / 2];
     uint32_t *hv = list + cap;
 
     for (;;) {

@@ -50,3 +50,19 @@ def test_batch_equals_single_calls():
     for q, cost, plan in zip(queries, res.costs, res.plans):
         one = mpdp.mpdp_optimize(q, mpdp.MPDP_COST_PGLIKE)
         assert cost == one.cost and plan == one.plan, q.name
+
+
+def test_batch_right_after_single_query_kernels():
+    """A batch launched right after the single-query kernels (the plan
+    extraction kernel last, whose LDS holds other data at the offsets the
+    batched kernel uses): every workgroup must size its set list from the
+    binomial table, not from LDS it has not filled yet.  Root costs against
+    the oracle."""
+    import oracle
+    for cm in (mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE):
+        mpdp.mpdp_optimize(W.star(16, 3), cm)
+        qs = W.batch_mixed(600, 17, n_range=(8, 14))
+        ws = mpdp.batch_workspace(qs)
+        r = mpdp.mpdp_optimize_batch(qs, cm, ws)
+        for q, c in zip(qs, r.costs):
+            assert np.float64(c).view(np.uint64) == np.float64(oracle.mpdp(q, cm).root_cost).view(np.uint64), q.name
