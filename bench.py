@@ -11,6 +11,18 @@ value      csg-cmp pairs (unordered) per second over the timed steps
            (#ccp = 24 * 2^23 = 201,326,592 per query, fixed by the graph)
 roofline   the dominant kernel's algorithmic bytes over its HIP-event time
 cpu_baseline  the CPU oracle (MPDP in plain C, one thread) on one query
+
+Besides the headline (timed region: the star-25 steps only), the same JSON
+line carries two untimed reports:
+batch      4096 mixed queries of 8-20 relations in one persistent launch:
+           kernel time, per-query latency p50/p99 (device clock from the
+           launch start), queries/s
+large      100-1000 relations (snowflake, depth 4, random cross edges):
+           GOO, IDP2 (k 15, 25), UnionDP (k 15) and the learned UnionDP
+           (k 15, scorer trained on the GPU first): plan cost normalized to
+           the best plan found per query, and optimization time; the learned
+           vs plain UnionDP cost ratio; and on held-out 20-26 relation
+           queries both UnionDPs' ratio to the exact optimum
 """
 from __future__ import annotations
 
@@ -28,7 +40,8 @@ sys.path.insert(0, ROOT)
 METRIC = "ccp pairs evaluated/sec + optimize time (ms) 25-rel star; learned vs plain cost ratio"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level_tree_star25.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2202_13511_amd", "csrc", "mpdp_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2202_13511_amd", "csrc", f)
+               for f in ("mpdp_kernels.hip", "mpdp_device.h", "mpdp_internal.h")]
 
 # Algorithmic bytes (per the memo layout: cost f64, card f64, left u32, op u8):
 #   per csg-cmp pair, C_out gathers the cost of the non-singleton side: 8 B
@@ -39,7 +52,10 @@ SET_BYTES = 21
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():
@@ -63,6 +79,8 @@ def main() -> int:
     ap.add_argument("--no-pglike", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter scaling)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -198,6 +216,12 @@ def main() -> int:
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nb
 
+    if not args.no_batch:
+        out["batch"] = bench_batch(mpdp, workloads, np)
+
+    if not args.no_large:
+        out["large"] = bench_large(mpdp, workloads, np)
+
     if not args.no_cpu_baseline:
         import oracle
         q = queries[0]
@@ -219,6 +243,82 @@ def main() -> int:
 
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_batch(mpdp, workloads, np, count=4096, runs=3):
+    """Config 4: one persistent launch over `count` mixed queries."""
+    import torch
+    qs = workloads.batch_mixed(count, 0)
+    ws = mpdp.batch_workspace(qs)
+    out = {}
+    for cm, name in ((mpdp.MPDP_COST_COUT, "C_out"), (mpdp.MPDP_COST_PGLIKE, "PG-like")):
+        mpdp.mpdp_optimize_batch(qs, cm, ws, flags=mpdp.MPDP_FLAG_TIMING)  # warm-up
+        best = None
+        for _ in range(runs):
+            t = time.perf_counter()
+            r = mpdp.mpdp_optimize_batch(qs, cm, ws, flags=mpdp.MPDP_FLAG_TIMING)
+            wall = (time.perf_counter() - t) * 1e3
+            if best is None or r.stats["ms_kernel"] < best[0].stats["ms_kernel"]:
+                best = (r, wall)
+        r, wall = best
+        lat = np.sort(r.latency_us)
+        out[name] = {
+            "kernel_ms": r.stats["ms_kernel"],
+            "call_ms": wall,
+            "queries_per_s": count / (r.stats["ms_kernel"] / 1e3),
+            "latency_us_p50": float(lat[len(lat) // 2]),
+            "latency_us_p99": float(lat[int(0.99 * (len(lat) - 1))]),
+            "latency_us_max": float(lat[-1]),
+            "ccp_pairs_per_s": r.stats["ccp_pairs"] / (r.stats["ms_kernel"] / 1e3),
+        }
+    del ws
+    torch.cuda.empty_cache()
+    return {"workload": f"{count} queries, n ~ U{{8..20}}, chain/star/cycle/snowflake/random mix, seed 0",
+            "workgroups": 512, "runs": runs, **out}
+
+
+def bench_large(mpdp, workloads, np):
+    """Config 5: heuristics on 100-1000 relations; learned vs plain UnionDP."""
+    from paper_2202_13511_amd import scorer
+    M = mpdp
+    methods = [("goo", M.MPDP_LARGE_GOO, 2), ("idp2_15", M.MPDP_LARGE_IDP2, 15), ("idp2_25", M.MPDP_LARGE_IDP2, 25),
+               ("uniondp_15", M.MPDP_LARGE_UNIONDP, 15), ("learned_uniondp_15", M.MPDP_LARGE_UNIONDP_LEARNED, 15)]
+    res = {"workload": "large_snowflake(n, seed): depth <= 4, round(n/20) cross edges; n in {100, 300, 1000}, "
+                       "seeds 0..2; costs normalized to the best plan found per query",
+           "train": {}, "cost_models": {}}
+    for cm, cname in ((M.MPDP_COST_COUT, "C_out"), (M.MPDP_COST_PGLIKE, "PG-like")):
+        t = time.perf_counter()
+        block, log = scorer.train(cm, seed=1, queries=300, rounds=4, steps=3000)
+        res["train"][cname] = {"seconds": time.perf_counter() - t, "examples": log.examples[-1],
+                               "final_loss": log.loss[-1]}
+        per_n = {}
+        ratios_lp = []
+        for n in (100, 300, 1000):
+            rows = {name: [] for name, _, _ in methods}
+            times = {name: [] for name, _, _ in methods}
+            for seed in range(3):
+                q = workloads.large_snowflake(n, seed)
+                costs = {}
+                for name, meth, k in methods:
+                    t = time.perf_counter()
+                    r = M.mpdp_optimize_large(q, cm, meth, k, scorer=block if "learned" in name else None)
+                    times[name].append((time.perf_counter() - t) * 1e3)
+                    costs[name] = r.cost
+                best = min(costs.values())
+                for name in costs:
+                    rows[name].append(costs[name] / best)
+                ratios_lp.append(costs["learned_uniondp_15"] / costs["uniondp_15"])
+            per_n[str(n)] = {name: {"cost_ratio_mean": float(np.mean(rows[name])),
+                                    "ms_mean": float(np.mean(times[name]))} for name in rows}
+        held = scorer.training_queries(40, 99)
+        plain, learned = scorer.compare_small(block, cm, held, 15)
+        res["cost_models"][cname] = {
+            "by_n": per_n,
+            "learned_vs_plain_uniondp_geomean": float(np.exp(np.mean(np.log(ratios_lp)))),
+            "small_vs_exact_geomean": {"uniondp_15": float(np.exp(np.mean(np.log(plain)))),
+                                       "learned_uniondp_15": float(np.exp(np.mean(np.log(learned))))},
+        }
+    return res
 
 
 if __name__ == "__main__":

@@ -88,7 +88,7 @@ def test_trained_scorer_against_plain_uniondp():
     under C_out.  The run is deterministic (fixed draws, no atomics in the
     gradient sums), so the comparison is stable."""
     from paper_2202_13511_amd import scorer
-    block, log = scorer.train(mpdp.MPDP_COST_COUT, seed=1, queries=200, rounds=3, steps=2000)
+    block, log = scorer.train(mpdp.MPDP_COST_COUT, seed=1, queries=300, rounds=4, steps=3000)
     print("train", log, flush=True)
     assert log.loss[-1] < 0.5 * 0.693  # well below the loss of a constant guess
     held = scorer.training_queries(40, 99)
