@@ -90,6 +90,14 @@ typedef struct {
 
 /* Flags for mpdp_optimize_ws. */
 #define MPDP_FLAG_TIMING 1u   /* time the filter and evaluate kernels with HIP events */
+/* Ablations (measurement only; plans, costs and ccp counts are unchanged):
+ * DPSUB      every connected set takes DPSUB's vertex-based candidates (Alg. 1:
+ *            every subset holding its lowest relation, CCP-checked) instead of
+ *            Alg. 2/3's block-local ones; evaluated_pairs counts 2^|S| - 2 per set
+ * NO_COMPACTION  tree joins: each lane evaluates the connected candidates it
+ *            unranked instead of compacting them through the wave's LDS ring */
+#define MPDP_FLAG_ABLATE_DPSUB 2u
+#define MPDP_FLAG_ABLATE_NO_COMPACTION 4u
 
 /* Status string for an mpdp_status value (static storage, never NULL). */
 const char *mpdp_status_str(mpdp_status s);
@@ -137,7 +145,7 @@ mpdp_status mpdp_optimize(uint32_t n, uint32_t m, const mpdp_edge *edges,
  *                 bytes, 256-byte aligned; contents on entry are ignored
  *   ws_bytes      its size (MPDP_ENOMEM if too small)
  *   hip_stream    hipStream_t to enqueue on (NULL: the null stream)
- *   flags         0 or MPDP_FLAG_TIMING
+ *   flags         0, or MPDP_FLAG_TIMING and the ablation flags
  * All kernels run on hip_stream; the call waits for that stream before it
  * returns because the plan is delivered to host memory.  Concurrent calls
  * must use distinct workspaces.  After MPDP_OK the memo stays readable in the
@@ -163,6 +171,22 @@ mpdp_status mpdp_optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges,
                                 const double *base_costs, mpdp_cost_model cost_model,
                                 void *d_workspace, size_t ws_bytes, void *hip_stream, uint32_t flags,
                                 mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out);
+
+/*
+ * The same exact DP on the host's cores (the all-cores CPU baseline of the
+ * measurements; Section 3.3 hands out work items through an atomic
+ * counter): every level's colex rank range is cut into chunks that
+ * `threads` threads (0: all hardware threads) take from an atomic counter;
+ * enumeration, card(S), costs and the plan key are those above, so the
+ * plan and cost equal the GPU's bit for bit.  Dense memo of 2^n entries in
+ * host memory; n <= 28 (MPDP_ETOOLARGE beyond); no HIP call.  Arguments and
+ * errors otherwise as mpdp_optimize; stats_out->eval_launches holds the
+ * thread count.
+ */
+mpdp_status mpdp_optimize_cpu(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                              const double *cardinalities, const double *selectivities,
+                              mpdp_cost_model cost_model, uint32_t threads, mpdp_plan_node *plan_out,
+                              double *cost_out, mpdp_stats *stats_out);
 
 /*
  * Batched optimization: many small queries in one launch.

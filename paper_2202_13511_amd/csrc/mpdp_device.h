@@ -389,6 +389,23 @@ struct SetBlocks {
 // chunks of 2^shift, with the smallest shift (up to 4) that leaves at most
 // `budget` chunks, so that the candidates of a small set still spread over
 // all the lanes that take part.
+// DPSUB's enumeration (ablation): S itself is the only block, no cut vertex.
+__device__ SetBlocks whole_set(uint32_t S, WaveScratch &W, int lane, uint32_t budget) {
+    const int k = popc32(S);
+    const uint32_t half = (1u << (k - 1)) - 1u;
+    uint32_t shift = 4;
+    for (uint32_t sh = 0; sh <= 4; ++sh)
+        if (((half + (1u << sh) - 1u) >> sh) <= budget) { shift = sh; break; }
+    const uint32_t chunks = (half + (1u << shift) - 1u) >> shift;
+    if (lane == 0) {
+        W.blk[0] = S;
+        W.full[0] = 0;
+        W.cpre[0] = 0;
+        W.cpre[1] = chunks;
+    }
+    return SetBlocks{0u, chunks, shift, (half + 15u) >> 4, (1ull << k) - 2ull};
+}
+
 __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, int lane, uint32_t budget) {
     const bool mine = lane < 32 && ((S >> lane) & 1u);
     const uint32_t adjS = mine ? (L.adj[lane] & S) : 0u;
@@ -603,7 +620,7 @@ __device__ __forceinline__ uint64_t memo_index_t(const uint32_t *binom, const ui
 // its LDS ring in rank order and evaluates 64 of them at a time, one per
 // lane, so no lane idles on a disconnected candidate.  Returns the number of
 // connected sets it found (uniform across the wave).
-template <int CM, int kTreeChunk>
+template <int CM, int kTreeChunk, bool kCompact = true>
 __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
                                     uint64_t w0, uint64_t wstride, uint32_t *ring, uint32_t lane) {
     static_assert(kRing >= 63 + 64 * kTreeChunk, "ring too small");
@@ -632,6 +649,14 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         for (int b = 0; b < 3; ++b)  // exclusive prefix of `mine` (<= 4) across the wave
             before += (uint32_t)__popcll(__ballot((mine >> b) & 1u) & below_me) << b;
         const uint32_t total = (uint32_t)__shfl((int)(before + mine), 63);
+        if (!kCompact) {  // ablation: each lane evaluates the sets it kept, lanes diverge
+#pragma unroll
+            for (int j = 0; j < kTreeChunk; ++j)
+                if (keep & (1u << j)) eval_tree_set<CM>(L, M, sets[j], off_k, cost_km1, card_km1);
+            tail += total;
+            head = tail;
+            continue;
+        }
         uint32_t pos = tail + before;
 #pragma unroll
         for (int j = 0; j < kTreeChunk; ++j)
@@ -660,7 +685,8 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
 // lane's counts are prefixed across the wave with one ballot per count bit
 // and one atomic per list and wave (global or LDS) reserves the range.
 __device__ void filter_wave(const LdsGraph &L, int n, uint32_t k, uint64_t ncand, uint64_t w0, uint64_t wstride,
-                            uint32_t *list, uint32_t cap, uint32_t *ntree, uint32_t *ngen, uint32_t lane) {
+                            uint32_t *list, uint32_t cap, uint32_t *ntree, uint32_t *ngen, uint32_t lane,
+                            bool split = true) {
     const unsigned long long below_me = (1ull << lane) - 1ull;
     const uint64_t per_wave = 64ull * kFilterChunk;
     for (uint64_t w = w0; w * per_wave < ncand; w += wstride) {
@@ -673,7 +699,7 @@ __device__ void filter_wave(const LdsGraph &L, int n, uint32_t k, uint64_t ncand
             sets[j] = S;
             if (r0 + (uint64_t)j < ncand) {
                 if (grow(L.nb, lowbit(S), S) == S) {
-                    if (induces_tree(L, S)) keep_t |= 1u << j;
+                    if (split && induces_tree(L, S)) keep_t |= 1u << j;
                     else keep_g |= 1u << j;
                 }
                 S = next_subset(S);
@@ -716,7 +742,8 @@ __device__ void filter_wave(const LdsGraph &L, int n, uint32_t k, uint64_t ncand
 template <int CM>
 __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *list, uint32_t cap, uint32_t ntree,
                            uint32_t ngen, uint32_t w0, uint32_t wstride, WaveScratch &W, uint32_t *heavy,
-                           uint32_t *nheavy, uint32_t lane, unsigned long long &ccp, unsigned long long &evaluated) {
+                           uint32_t *nheavy, uint32_t lane, unsigned long long &ccp, unsigned long long &evaluated,
+                           bool dpsub = false) {
     const uint32_t groups = (ntree + 63u) >> 6;
     for (uint32_t i = w0; i < groups + ngen; i += wstride) {
         if (i < groups) {
@@ -729,7 +756,7 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
             continue;
         }
         const uint32_t S = list[cap - 1u - (i - groups)];
-        const SetBlocks sb = analyze_set(L, S, W, (int)lane, 64u);
+        const SetBlocks sb = dpsub ? whole_set(S, W, (int)lane, 64u) : analyze_set(L, S, W, (int)lane, 64u);
         if (sb.chunks16 > kHeavyChunks) {
             if (lane == 0) heavy[atomicAdd(nheavy, 1u)] = S;
             wave_sync_lds();

@@ -212,6 +212,8 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     EventPool ev;
     if (timing) HIPCHK(ev.make(4 * (size_t)n));
 
+    DevGraph *hg = const_cast<DevGraph *>(&q.g);
+    hg->ablate = (flags & MPDP_FLAG_ABLATE_DPSUB) ? mpdp::kAblateDpsub : 0u;
     HIPCHK(hipMemcpyAsync(dg, &q.g, sizeof(DevGraph), hipMemcpyHostToDevice, s));
     HIPCHK(mpdp::launch_init(dg, n, memo, cnt, s));
     const bool general = force_general || !q.is_tree;
@@ -226,7 +228,8 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         if (general)
             HIPCHK(mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, heavy, cnt, memo, s));
         else  // tree joins: unrank, filter and evaluate in one kernel per level
-            HIPCHK(mpdp::launch_level_tree(dg, q.cost_model, k, nc, cnt, memo, s));
+            HIPCHK(mpdp::launch_level_tree(dg, q.cost_model, k, nc, (flags & MPDP_FLAG_ABLATE_NO_COMPACTION) == 0, cnt,
+                                           memo, s));
         ++launches;
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 6], s));
     }
@@ -565,7 +568,7 @@ mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges, con
     }
     if (!d_workspace) return MPDP_EINVAL;
     return run(q, d_workspace, ws_bytes, static_cast<hipStream_t>(hip_stream), flags, plan_out, cost_out,
-               stats_out, t0, (flags & kFlagForceGeneral) != 0);
+               stats_out, t0, (flags & (kFlagForceGeneral | MPDP_FLAG_ABLATE_DPSUB)) != 0);
 }
 
 mpdp_status mpdp_optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,

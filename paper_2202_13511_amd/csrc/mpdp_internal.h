@@ -35,6 +35,7 @@ static_assert(sizeof(LdsImage) % 16 == 0, "LdsImage is copied in 16-byte units")
 struct DevGraph {
     LdsImage lds;
     uint32_t n, m, is_tree, cost_model;
+    uint32_t ablate, pad[3];             // kAblateDpsub: every connected set is one block (DPSUB's enumeration)
     double sel_full[kMaxRel * kMaxRel];  // sel[u * 32 + v], symmetric, 0 without an edge
 };
 
@@ -89,7 +90,9 @@ hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev
 hipError_t launch_init(const DevGraph *g, uint32_t n, MemoPtrs memo, Counters *cnt, hipStream_t s);
 hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t *list, Counters *cnt,
                          hipStream_t s);
-hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
+constexpr uint32_t kAblateDpsub = 1u;
+
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, Counters *cnt,
                              MemoPtrs memo, hipStream_t s);
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
                                const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, hipStream_t s);

@@ -43,14 +43,14 @@ __global__ void k_init(const DevGraph *g, uint32_t n, MemoPtrs M, Counters *cnt)
 // same-popcount successor), appends the connected sets to its LDS ring in
 // rank order, and evaluates 64 of them at a time, one per lane, so no lane
 // idles on a disconnected candidate.
-template <int CM, int kTreeChunk>
+template <int CM, int kTreeChunk, bool kCompact>
 __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32_t k, uint64_t ncand,
                                                        Counters *cnt, MemoPtrs M) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ uint32_t ring_all[kWaves][kRing];
     stage_graph(g, L);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t found = level_tree_wave<CM, kTreeChunk>(
+    const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact>(
         L, M, (int)g->n, k, ncand, (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6),
         (uint64_t)gridDim.x * kWaves, ring_all[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(const DevGraph *g, uint32_t k
     const uint32_t n = g->n;
     filter_wave(L, (int)n, k, ncand, (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6),
                 (uint64_t)gridDim.x * kWaves, list, L.binom[n * 33 + n / 2], &cnt->level_count[k],
-                &cnt->general_count[k], threadIdx.x & 63u);
+                &cnt->general_count[k], threadIdx.x & 63u, (g->ablate & kAblateDpsub) == 0);
 }
 
 // Light work of a block-based level: groups of 64 tree-inducing sets, one
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
     unsigned long long my_ccp = 0, my_eval = 0;
     light_sets<CM>(L, M, list, L.binom[n * 33 + n / 2], cnt->level_count[k], cnt->general_count[k],
                    blockIdx.x * kWaves + (threadIdx.x >> 6), gridDim.x * kWaves, WS[threadIdx.x >> 6], heavy,
-                   &cnt->heavy_count[k], lane, my_ccp, my_eval);
+                   &cnt->heavy_count[k], lane, my_ccp, my_eval, (g->ablate & kAblateDpsub) != 0);
 
     // one atomic per wave for the counters
     for (int off = 32; off >= 1; off >>= 1) {
@@ -113,7 +113,8 @@ __global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, u
     for (uint32_t h = blockIdx.x; h < count; h += gridDim.x) {
         const uint32_t S = heavy[h];
         if (wave == 0) {
-            const SetBlocks sb = analyze_set(L, S, W, lane, kHeavyBlock);
+            const SetBlocks sb = (g->ablate & kAblateDpsub) ? whole_set(S, W, lane, kHeavyBlock)
+                                                            : analyze_set(L, S, W, lane, kHeavyBlock);
             if (lane == 0) { sbs = sb; my_eval += sb.evaluated; }
         }
         __syncthreads();
@@ -176,7 +177,7 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, Counters *cnt,
                              MemoPtrs memo, hipStream_t s) {
     // Fewer consecutive ranks per lane on small levels, so that even they
     // spread over some thousands of waves; a persistent-sized grid on large
@@ -185,8 +186,13 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
     const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > kPersistGrid ? kPersistGrid : blocks));
-#define MPDP_LEVEL_TREE(CMV, CH) \
-    hipLaunchKernelGGL((k_level_tree<CMV, CH>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo)
+#define MPDP_LEVEL_TREE(CMV, CH)                                                                        \
+    do {                                                                                                \
+        if (compact)                                                                                    \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, true>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+    } while (0)
     if (cost_model == MPDP_COST_COUT) {
         if (chunk == 4) MPDP_LEVEL_TREE(MPDP_COST_COUT, 4);
         else if (chunk == 2) MPDP_LEVEL_TREE(MPDP_COST_COUT, 2);

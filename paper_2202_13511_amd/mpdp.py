@@ -21,10 +21,11 @@ MPDP_OK, MPDP_EINVAL, MPDP_ENOTCONNECTED, MPDP_ETOOLARGE, MPDP_ENOMEM, MPDP_EDEV
 MPDP_COST_COUT, MPDP_COST_PGLIKE = 0, 1
 MPDP_OP_SCAN, MPDP_OP_HASH, MPDP_OP_NESTLOOP, MPDP_OP_JOIN = 0, 1, 2, 3
 MPDP_FLAG_TIMING = 1
+MPDP_FLAG_ABLATE_DPSUB, MPDP_FLAG_ABLATE_NO_COMPACTION = 2, 4
 _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
-            "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
+            "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_optimize_cpu", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
             "mpdp_optimize_large", "mpdp_large_examples", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
             "mpdp_scorer_load", "mpdp_scorer_forward", "mpdp_scorer_grad", "mpdp_scorer_train_step"]
 SCORER_IN, SCORER_HIDDEN = 32, 256
@@ -109,6 +110,8 @@ def load(path: str = LIB_PATH):
     L.mpdp_optimize.restype = ctypes.c_int
     L.mpdp_optimize_ws.argtypes = common + [vp, sz, vp, u32] + outs
     L.mpdp_optimize_ws.restype = ctypes.c_int
+    L.mpdp_optimize_cpu.argtypes = common + [u32] + outs
+    L.mpdp_optimize_cpu.restype = ctypes.c_int
     L.mpdp_optimize_units.argtypes = common[:5] + [f64p, ctypes.c_int, vp, sz, vp, u32] + outs
     L.mpdp_optimize_units.restype = ctypes.c_int
     L.mpdp_optimize_large.argtypes = common + [ctypes.c_int, u32, vp, vp, ctypes.POINTER(mpdp_large_node), f64p,
@@ -203,6 +206,20 @@ def mpdp_optimize(query, cost_model: int = MPDP_COST_COUT) -> Result:
     stats = mpdp_stats()
     st = load().mpdp_optimize(int(n), m, ep, cp, sp, int(cost_model), plan, ctypes.byref(cost),
                               ctypes.byref(stats))
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    return _result(n, plan, cost, stats)
+
+
+def mpdp_optimize_cpu(query, cost_model: int = MPDP_COST_COUT, threads: int = 0) -> Result:
+    """The exact DP on the host's cores (threads = 0: all hardware threads)."""
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    plan = (mpdp_plan_node * max(2 * n - 1, 1))()
+    cost = ctypes.c_double()
+    stats = mpdp_stats()
+    st = load().mpdp_optimize_cpu(int(n), m, ep, cp, sp, int(cost_model), int(threads), plan, ctypes.byref(cost),
+                                  ctypes.byref(stats))
     if st != MPDP_OK:
         raise MpdpError(st, mpdp_status_str(st))
     return _result(n, plan, cost, stats)

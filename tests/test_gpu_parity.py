@@ -86,6 +86,27 @@ def test_block_kernel_on_trees(cm):
         check_stats(q, res, ref, general=True)
 
 
+@pytest.mark.parametrize("cm", CMS)
+def test_ablations_leave_results_unchanged(cm):
+    """The measurement-only ablations (DPSUB's vertex-based candidates on the
+    GPU; the tree kernel without LDS compaction) reach the oracle's memo bit
+    for bit; DPSUB evaluates 2^|S| - 2 candidates per connected set (the
+    oracle's DPSUB also counts the empty and the full subset)."""
+    for q in [W.star(11, 4), W.snowflake(14, 5), W.cycle_chords(2, n=11, chords=3), W.clique(8, 1),
+              W.random_connected(11, 3, 0.3)]:
+        ref = oracle.mpdp(q, cm)
+        res, gm = run_ws(q, cm, flags=mpdp.MPDP_FLAG_ABLATE_DPSUB)
+        check_memo(q, gm, ref)
+        check_plan(q, res, ref)
+        d = oracle.dpsub(q, cm)
+        assert res.stats["evaluated_pairs"] == d.evaluated - 2 * d.connected_sets, q.name
+        assert 2 * res.stats["ccp_pairs"] == ref.ccp_ordered, q.name
+        if q.m == q.n - 1:
+            res, gm = run_ws(q, cm, flags=mpdp.MPDP_FLAG_ABLATE_NO_COMPACTION)
+            check_memo(q, gm, ref)
+            check_plan(q, res, ref)
+
+
 def test_self_allocating_entry_point():
     q = W.cycle_chords(7, n=12, chords=5)
     res = mpdp.mpdp_optimize(q, mpdp.MPDP_COST_PGLIKE)
