@@ -23,6 +23,10 @@ large      100-1000 relations (snowflake, depth 4, random cross edges):
            the best plan found per query, and optimization time; the learned
            vs plain UnionDP cost ratio; and on held-out 20-26 relation
            queries both UnionDPs' ratio to the exact optimum
+ablations  the same optimizer with DPSUB's vertex-based candidates on the GPU,
+           and the tree kernel without its LDS compaction (results unchanged)
+cpu_allcores  the library's multi-threaded CPU MPDP on the star (16 threads
+           at most), next to the single-thread oracle of cpu_baseline
 """
 from __future__ import annotations
 
@@ -81,6 +85,7 @@ def main() -> int:
                     help="also run a plain device copy of this size (counter scaling)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -222,6 +227,17 @@ def main() -> int:
     if not args.no_large:
         out["large"] = bench_large(mpdp, workloads, np)
 
+    if not args.no_ablations:
+        out["ablations"] = bench_ablations(mpdp, workloads, dev)
+        threads = min(16, os.cpu_count() or 1)
+        q = queries[0]
+        t = time.perf_counter()
+        r = mpdp.mpdp_optimize_cpu(q, mpdp.MPDP_COST_COUT, threads)
+        cdt = time.perf_counter() - t
+        cpu_rate = r.stats["ccp_pairs"] / cdt
+        out["cpu_allcores"] = {"value": cpu_rate, "unit": "ccp pairs/s", "threads": threads,
+                               "optimize_ms": cdt * 1e3, "query": q.name, "gpu_speedup": value / cpu_rate}
+
     if not args.no_cpu_baseline:
         import oracle
         q = queries[0]
@@ -275,6 +291,36 @@ def bench_batch(mpdp, workloads, np, count=4096, runs=3):
     torch.cuda.empty_cache()
     return {"workload": f"{count} queries, n ~ U{{8..20}}, chain/star/cycle/snowflake/random mix, seed 0",
             "workgroups": 512, "runs": runs, **out}
+
+
+def bench_ablations(mpdp, workloads, dev, reps=5):
+    """Optimize time (min of reps) with and without the two enhancements."""
+    import torch
+
+    def best_ms(q, flags):
+        ws = mpdp.workspace(q.n, mpdp.MPDP_COST_COUT, dev)
+        mpdp.mpdp_optimize_ws(q, mpdp.MPDP_COST_COUT, ws, flags=flags)
+        ts, st = [], None
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = mpdp.mpdp_optimize_ws(q, mpdp.MPDP_COST_COUT, ws, flags=flags)
+            ts.append((time.perf_counter() - t) * 1e3)
+            st = r.stats
+        del ws
+        torch.cuda.empty_cache()
+        return min(ts), st
+
+    out = {"no_compaction": {}, "dpsub": {}}
+    for q in (workloads.star(25, 0), workloads.snowflake(25, 0)):
+        a, _ = best_ms(q, 0)
+        b, _ = best_ms(q, mpdp.MPDP_FLAG_ABLATE_NO_COMPACTION)
+        out["no_compaction"][q.name] = {"mpdp_ms": a, "ablated_ms": b, "slowdown": b / a}
+    for q in (workloads.star(20, 0), workloads.snowflake(20, 1), workloads.clique(14, 0)):
+        a, sa = best_ms(q, 0)
+        b, sb = best_ms(q, mpdp.MPDP_FLAG_ABLATE_DPSUB)
+        out["dpsub"][q.name] = {"mpdp_ms": a, "dpsub_ms": b, "slowdown": b / a,
+                                "mpdp_candidates": sa["evaluated_pairs"], "dpsub_candidates": sb["evaluated_pairs"]}
+    return out
 
 
 def bench_large(mpdp, workloads, np):
