@@ -202,16 +202,23 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
                                               const double *__restrict__ cost_km1,
                                               const double *__restrict__ card_km1) {
     constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 8 : 4;
+    // one pass over S: its colex rank, the sum of C(s_i, i), and card(S) in
+    // card_of's order (members ascending, each card then its selectivities)
     uint32_t rank = 0, bsum = 0;
+    double c = 1.0;
     {
         int i = 0;
         for (uint32_t T = S; T; T &= T - 1, ++i) {
             const int v = ctz32(T);
             rank += L.binom[v * 33 + i + 1];
             bsum += L.binom[v * 33 + i];
+            c = c * L.card[v];
+            const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+            for (uint32_t U = lower & S; U; U &= U - 1)
+                c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
         }
     }
-    const double cardS = card_of(L, S);
+    const double cardS = c < 1.0 ? 1.0 : c;
     Key best = worst_key();
     uint32_t pa = 0, pb = 0, T = S;
     int i = 0;

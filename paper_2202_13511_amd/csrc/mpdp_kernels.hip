@@ -182,7 +182,7 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
     // Fewer consecutive ranks per lane on small levels, so that even they
     // spread over some thousands of waves; a persistent-sized grid on large
     // ones, so each workgroup stages the query information once.
-    constexpr uint64_t kWantWaves = 8192;
+    constexpr uint64_t kWantWaves = 1024;
     const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > kPersistGrid ? kPersistGrid : blocks));
