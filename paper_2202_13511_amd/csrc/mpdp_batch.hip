@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 if (t == 0) s_level = 0;
                 __syncthreads();
                 const uint32_t found =
-                    level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, rings[wave], lane);
+                    level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 255) / 256, rings[wave], lane);
                 if (lane == 0 && found) atomicAdd(&s_level, found);
                 __syncthreads();
                 if (t == 0) {

@@ -191,15 +191,34 @@ __device__ __forceinline__ void eval_vals(uint32_t A, uint32_t B, double cA, dou
 
 // Alg. 2 for one connected S of a tree join graph.  With the tree rooted at
 // relation 0, removing the edge (parent(c), c) of G[S] gives the pair
-// (desc(c) & S, S minus that) for every c in S whose parent is in S.
-// When desc(c) & S = {c} the complement's colex rank follows from prefix
-// sums, rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and the
-// singleton's cost and card come from LDS.  Pairs are taken in batches of
-// kPairBatch whose memo gathers are all issued before any is used; the batch
-// keeps 32-bit ranks only, so that eight waves fit on a SIMD.
+// (desc(c) & S, S minus that) for every c in S whose parent is in S, which
+// is every member but the topmost one.  When desc(c) & S = {c} the
+// complement's colex rank follows from prefix sums,
+// rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and the
+// singleton's cost and card come from LDS.
+//
+// Every set of the level has k members and k is the same on all lanes, so
+// the member loops run a uniform k times (scalar branches only).  Members
+// go in batches of kPairBatch whose memo gathers are all issued before any
+// is used; the topmost member stays in its batch as an empty slot (A = 0)
+// that gathers a harmless singleton and offers nothing.
 template <int CM>
-__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint64_t off_k,
-                                              const double *__restrict__ cost_km1,
+__device__ __forceinline__ bool key_less_sel(unsigned long long ac, uint32_t al, uint32_t aop, const Key &b) {
+    return (ac < b.c) | ((ac == b.c) & ((al < b.l) | ((al == b.l) & (aop < b.op))));
+}
+
+template <int CM>
+__device__ __forceinline__ void offer_if(bool on, Key &best, double cost, uint32_t left, uint32_t op) {
+    const unsigned long long c = (unsigned long long)__double_as_longlong(cost);
+    const bool take = on & key_less_sel<CM>(c, left, op, best);
+    best.c = take ? c : best.c;
+    best.l = take ? left : best.l;
+    best.op = take ? op : best.op;
+}
+
+template <int CM>
+__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t k,
+                                              uint64_t off_k, const double *__restrict__ cost_km1,
                                               const double *__restrict__ card_km1) {
     constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 8 : 4;
     // one pass over S: its colex rank, the sum of C(s_i, i), and card(S) in
@@ -207,9 +226,10 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
     uint32_t rank = 0, bsum = 0;
     double c = 1.0;
     {
-        int i = 0;
-        for (uint32_t T = S; T; T &= T - 1, ++i) {
+        uint32_t T = S;
+        for (uint32_t i = 0; i < k; ++i) {
             const int v = ctz32(T);
+            T &= T - 1;
             rank += L.binom[v * 33 + i + 1];
             bsum += L.binom[v * 33 + i];
             c = c * L.card[v];
@@ -221,39 +241,32 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
     const double cardS = c < 1.0 ? 1.0 : c;
     Key best = worst_key();
     uint32_t pa = 0, pb = 0, T = S;
-    int i = 0;
-    while (T) {
+    for (uint32_t i0 = 0; i0 < k; i0 += kPairBatch) {
         uint32_t Av[kPairBatch], rk[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
             Av[u] = 0;
             rk[u] = 0;
-            while (T) {
-                const int c = ctz32(T);
+            const uint32_t i = i0 + (uint32_t)u;
+            if (i < k) {
+                const int m = ctz32(T);
                 T &= T - 1;
-                const uint32_t a_i = L.binom[c * 33 + i + 1];
-                pb += L.binom[c * 33 + i];
-                ++i;
-                const bool take = (S & L.pbit[c]) != 0;
-                if (take) {
-                    Av[u] = L.desc[c] & S;
-                    rk[u] = pa + (bsum - pb);  // colex rank of S - {c}
-                }
-                pa += a_i;
-                if (take) break;
+                pb += L.binom[m * 33 + i];
+                rk[u] = pa + (bsum - pb);  // colex rank of S - {m}
+                pa += L.binom[m * 33 + i + 1];
+                Av[u] = (S & L.pbit[m]) ? (L.desc[m] & S) : 0u;
             }
         }
         double cA[kPairBatch], cB[kPairBatch], kA[kPairBatch], kB[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
             const uint32_t A = Av[u];
-            if (!A) continue;
-            if ((A & (A - 1)) == 0) {
+            if ((A & (A - 1)) == 0) {  // a singleton, or the empty slot
                 cB[u] = cost_km1[rk[u]];
                 if (CM != MPDP_COST_COUT) kB[u] = card_km1[rk[u]];
-                const int c = ctz32(A);
-                cA[u] = L.bcost[c];
-                kA[u] = L.card[c];
+                const int m = ctz32(A | 0x80000000u);
+                cA[u] = L.bcost[m & 31];
+                kA[u] = L.card[m & 31];
             } else {
                 const uint64_t ia = memo_index(L, A), ib = memo_index(L, S ^ A);
                 cA[u] = M.cost[ia];
@@ -265,8 +278,23 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
             }
         }
 #pragma unroll
-        for (int u = 0; u < kPairBatch; ++u)
-            if (Av[u]) eval_vals<CM>(Av[u], S ^ Av[u], cA[u], cB[u], kA[u], kB[u], cardS, best);
+        for (int u = 0; u < kPairBatch; ++u) {
+            const uint32_t A = Av[u], B = S ^ A;
+            const bool on = A != 0;
+            const double base = cA[u] + cB[u];
+            if (CM == MPDP_COST_COUT) {
+                offer_if<CM>(on, best, base + cardS, A < B ? A : B, MPDP_OP_JOIN);
+            } else {
+                const double out = 0.01 * cardS;
+                const double hjA = ((base + 0.0125 * kB[u]) + 0.0025 * kA[u]) + out;  // A outer, B hashed
+                const double nlA = (base + (0.0025 * kA[u]) * kB[u]) + out;
+                const double hjB = ((base + 0.0125 * kA[u]) + 0.0025 * kB[u]) + out;  // B outer, A hashed
+                const double nlB = (base + (0.0025 * kB[u]) * kA[u]) + out;
+                const bool hA = hjA <= nlA, hB = hjB <= nlB;
+                offer_if<CM>(on, best, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                offer_if<CM>(on, best, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+            }
+        }
     }
     store_best(M, off_k + rank, best, cardS);
 }
@@ -621,15 +649,15 @@ __device__ __forceinline__ uint64_t memo_index_t(const uint32_t *binom, const ui
 
 
 // One wave's share of an Alg. 2 level (unrank, filter, evaluate, prune and
-// scatter fused): it walks the ranges w0, w0 + wstride, ... of 64 *
-// kTreeChunk colex ranks (kTreeChunk consecutive ranks per lane: unrank the
+// scatter fused): it walks the ranges w0, w0 + wstride, ... (below wend) of
+// 64 * kTreeChunk colex ranks (kTreeChunk consecutive ranks per lane: unrank the
 // first, then the same-popcount successor), appends the connected sets to
 // its LDS ring in rank order and evaluates 64 of them at a time, one per
 // lane, so no lane idles on a disconnected candidate.  Returns the number of
 // connected sets it found (uniform across the wave).
 template <int CM, int kTreeChunk, bool kCompact = true>
 __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
-                                    uint64_t w0, uint64_t wstride, uint32_t *ring, uint32_t lane) {
+                                    uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *ring, uint32_t lane) {
     static_assert(kRing >= 63 + 64 * kTreeChunk, "ring too small");
     const unsigned long long below_me = (1ull << lane) - 1ull;
     const uint64_t per_wave = 64ull * kTreeChunk;
@@ -637,7 +665,7 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
     const double *cost_km1 = M.cost + off_km1;
     const double *card_km1 = M.card + off_km1;
     uint32_t head = 0, tail = 0;  // ring cursors, uniform across the wave
-    for (uint64_t w = w0; w * per_wave < ncand; w += wstride) {
+    for (uint64_t w = w0; w < wend; w += wstride) {
         const uint64_t r0 = w * per_wave + (uint64_t)lane * kTreeChunk;
         uint32_t S = r0 < ncand ? colex_unrank(L.binom, n, (int)k, (uint32_t)r0) : 0u;
         uint32_t sets[kTreeChunk];
@@ -659,7 +687,7 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         if (!kCompact) {  // ablation: each lane evaluates the sets it kept, lanes diverge
 #pragma unroll
             for (int j = 0; j < kTreeChunk; ++j)
-                if (keep & (1u << j)) eval_tree_set<CM>(L, M, sets[j], off_k, cost_km1, card_km1);
+                if (keep & (1u << j)) eval_tree_set<CM>(L, M, sets[j], k, off_k, cost_km1, card_km1);
             tail += total;
             head = tail;
             continue;
@@ -672,14 +700,14 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         wave_sync_lds();
         while (tail - head >= 64) {
             const uint32_t s = ring[(head + lane) % kRing];
-            eval_tree_set<CM>(L, M, s, off_k, cost_km1, card_km1);
+            eval_tree_set<CM>(L, M, s, k, off_k, cost_km1, card_km1);
             head += 64;
         }
         wave_sync_lds();
     }
     if (tail != head && lane < tail - head) {
         const uint32_t s = ring[(head + lane) % kRing];
-        eval_tree_set<CM>(L, M, s, off_k, cost_km1, card_km1);
+        eval_tree_set<CM>(L, M, s, k, off_k, cost_km1, card_km1);
     }
     wave_sync_lds();
     return tail;

@@ -50,9 +50,25 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     __shared__ uint32_t ring_all[kWaves][kRing];
     stage_graph(g, L);
     const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t per_wave = 64ull * kTreeChunk;
+    const uint64_t nw = (ncand + per_wave - 1) / per_wave;
+    // Workgroups are dealt to the eight XCDs round robin (workgroup b runs on
+    // XCD b mod 8).  When the grid divides evenly, each XCD sweeps its own
+    // contiguous eighth of the level's ranks, so the neighbouring colex ranks
+    // of level k-1 that those sets gather sit in one XCD's L2.
+    uint64_t w0, ws, we;
+    if (gridDim.x & 7u) {
+        w0 = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+        ws = (uint64_t)gridDim.x * kWaves;
+        we = nw;
+    } else {
+        const uint64_t x = blockIdx.x & 7u;
+        w0 = nw * x / 8 + (uint64_t)(blockIdx.x >> 3) * kWaves + (threadIdx.x >> 6);
+        ws = (uint64_t)(gridDim.x >> 3) * kWaves;
+        we = nw * (x + 1) / 8;
+    }
     const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact>(
-        L, M, (int)g->n, k, ncand, (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6),
-        (uint64_t)gridDim.x * kWaves, ring_all[threadIdx.x >> 6], lane);
+        L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
 
