@@ -242,20 +242,26 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
     Key best = worst_key();
     uint32_t pa = 0, pb = 0, T = S;
     for (uint32_t i0 = 0; i0 < k; i0 += kPairBatch) {
-        uint32_t Av[kPairBatch], rk[kPairBatch];
+        // members i0 .. i0 + kPairBatch - 1 (slots past k read relation
+        // 31's entries, which exist, and are masked); all LDS reads of the
+        // batch are issued before any is used
+        uint32_t Av[kPairBatch], rk[kPairBatch], ba[kPairBatch], bb[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
-            Av[u] = 0;
-            rk[u] = 0;
+            const int m = ctz32(T | 0x80000000u);
+            T &= T - 1;
             const uint32_t i = i0 + (uint32_t)u;
-            if (i < k) {
-                const int m = ctz32(T);
-                T &= T - 1;
-                pb += L.binom[m * 33 + i];
-                rk[u] = pa + (bsum - pb);  // colex rank of S - {m}
-                pa += L.binom[m * 33 + i + 1];
-                Av[u] = (S & L.pbit[m]) ? (L.desc[m] & S) : 0u;
-            }
+            bb[u] = L.binom[m * 33 + i];
+            ba[u] = L.binom[m * 33 + i + 1];
+            const uint32_t par = L.pbit[m], below = L.desc[m];
+            Av[u] = ((i < k) & ((S & par) != 0)) ? (below & S) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            pb += bb[u];
+            // colex rank of S - {m}; a slot past the last member gathers entry 0
+            rk[u] = (i0 + (uint32_t)u < k) ? pa + (bsum - pb) : 0u;
+            pa += ba[u];
         }
         double cA[kPairBatch], cB[kPairBatch], kA[kPairBatch], kB[kPairBatch];
 #pragma unroll
