@@ -815,72 +815,92 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
     }
 }
 
-// Plan extraction scratch (LDS) and routine: lane 0 of the calling group
-// follows the left pointers from the full set (the only dependent chain,
-// n - 1 reads) and records the join nodes in post-order; then `nthreads`
-// threads fill cost, card and operator of every node.  Returns false if the
-// memo is inconsistent.
+// Plan extraction scratch (LDS) and routine.  Join nodes are numbered in
+// post-order (left subtree, right subtree, node), after the n relations.  A
+// node whose subtree covers S and starts after `start` finished join nodes
+// gets number n + start + |S| - 2; its left child L starts at `start`, its
+// right child at start + |L| - 1.  So numbers follow from set sizes alone
+// and wave 0 can walk the plan tree top-down one depth per round, every
+// node of the frontier reading its left set at once (the only dependent
+// chain is the tree's depth); then all `nthreads` threads fill cost, card
+// and operator of every node.  Returns false if the memo is inconsistent.
 struct PlanScratch {
     uint32_t node_set[64];
     int node_l[64], node_r[64];
-    int node_count;
+    uint32_t fr_set[2][32];
+    int fr_start[2][32];
+    int error;
 };
 
 __device__ bool extract_plan(const uint32_t *binom, const uint64_t *loff, const MemoPtrs &M, uint32_t n,
                              mpdp_plan_node *plan, double *root_cost, PlanScratch &P, uint32_t t,
                              uint32_t nthreads) {
     const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
-    if (t == 0) {
-        int next = (int)n;
-        if (n > 1) {
-            struct Frame { uint32_t S; uint32_t L; int stage; int li; };
-            Frame st[33];
-            int sp = 0, ret = -1, guard = 0;
-            st[sp++] = Frame{full, M.left[memo_index_t(binom, loff, full)], 0, -1};
-            while (sp > 0 && ++guard < 4 * 64) {
-                Frame &f = st[sp - 1];
-                const uint32_t Lft = f.L;
-                if (Lft == 0 || (Lft & ~f.S) != 0 || Lft == f.S) { next = -1; break; }
-                const uint32_t Rgt = f.S & ~Lft;
-                if (f.stage == 0) {
-                    f.stage = 1;
-                    if ((Lft & (Lft - 1)) == 0) ret = ctz32(Lft);
-                    else {
-                        if (sp >= 33) { next = -1; break; }
-                        st[sp++] = Frame{Lft, M.left[memo_index_t(binom, loff, Lft)], 0, -1};
-                        continue;
-                    }
-                }
-                if (f.stage == 1) {
-                    f.li = ret;
-                    f.stage = 2;
-                    if ((Rgt & (Rgt - 1)) == 0) ret = ctz32(Rgt);
-                    else {
-                        if (sp >= 33) { next = -1; break; }
-                        st[sp++] = Frame{Rgt, M.left[memo_index_t(binom, loff, Rgt)], 0, -1};
-                        continue;
-                    }
-                }
-                if (next >= 63) { next = -1; break; }
-                P.node_set[next] = f.S;
-                P.node_l[next] = f.li;
-                P.node_r[next] = ret;
-                ret = next++;
-                --sp;
-            }
-            if (next >= 0 && (sp != 0 || next != (int)(2 * n - 1))) next = -1;
+    if (t < 64) {
+        const uint32_t lane = t;
+        const unsigned long long below_me = (1ull << lane) - 1ull;
+        if (lane == 0) {
+            P.error = 0;
+            P.fr_set[0][0] = full;
+            P.fr_start[0][0] = 0;
         }
-        P.node_count = next;
-        *root_cost = M.cost[memo_index_t(binom, loff, full)];
+        wave_sync_lds();
+        int cur = 0;
+        uint32_t nfr = n > 1 ? 1u : 0u;  // frontier size, uniform; at most 31 join nodes per depth
+        bool bad = false;
+        for (uint32_t depth = 0; nfr != 0 && depth < n; ++depth) {
+            uint32_t push = 0, c0 = 0, c1 = 0;  // join children to visit next: c0, then c1
+            int s0 = 0, s1 = 0;
+            if (lane < nfr) {
+                const uint32_t S = P.fr_set[cur][lane];
+                const int st = P.fr_start[cur][lane];
+                const uint32_t Lft = M.left[memo_index_t(binom, loff, S)];
+                if (Lft == 0 || (Lft & ~S) != 0 || Lft == S) {
+                    bad = true;
+                } else {
+                    const uint32_t Rgt = S & ~Lft;
+                    const int nl = popc32(Lft), nr = popc32(Rgt);
+                    const int rst = st + nl - 1;
+                    const int idx = (int)n + st + popc32(S) - 2;
+                    P.node_set[idx] = S;
+                    P.node_l[idx] = nl >= 2 ? (int)n + st + nl - 2 : ctz32(Lft);
+                    P.node_r[idx] = nr >= 2 ? (int)n + rst + nr - 2 : ctz32(Rgt);
+                    if (nl >= 2) { c0 = Lft; s0 = st; push = 1; }
+                    if (nr >= 2) {
+                        if (push) { c1 = Rgt; s1 = rst; push = 2; }
+                        else { c0 = Rgt; s0 = rst; push = 1; }
+                    }
+                }
+            }
+            // exclusive prefix of `push` (<= 2) across the wave
+            const uint32_t before = (uint32_t)__popcll(__ballot(push & 1u) & below_me) +
+                                    2u * (uint32_t)__popcll(__ballot((push >> 1) & 1u) & below_me);
+            const uint32_t total = (uint32_t)__shfl((int)(before + push), 63);
+            const int nxt = cur ^ 1;
+            if (push >= 1 && before < 32) {
+                P.fr_set[nxt][before] = c0;
+                P.fr_start[nxt][before] = s0;
+            }
+            if (push >= 2 && before + 1 < 32) {
+                P.fr_set[nxt][before + 1] = c1;
+                P.fr_start[nxt][before + 1] = s1;
+            }
+            if (total > 32) bad = true;
+            wave_sync_lds();
+            nfr = total > 32 ? 0u : total;
+            cur = nxt;
+        }
+        if (nfr != 0) bad = true;
+        if (__ballot(bad) != 0ull && lane == 0) P.error = 1;
+        if (lane == 0) *root_cost = M.cost[memo_index_t(binom, loff, full)];
     }
     __syncthreads();
-    const int total = P.node_count;
-    if (total < 0) return false;
+    if (P.error) return false;
     for (uint32_t v = t; v < n; v += nthreads) {
         const uint64_t at = loff[1] + v;
         plan[v] = mpdp_plan_node{-1, -1, 1u << v, MPDP_OP_SCAN, M.cost[at], M.card[at]};
     }
-    for (int j = (int)n + (int)t; j < total; j += (int)nthreads) {
+    for (uint32_t j = n + t; j + 1 < 2 * n; j += nthreads) {
         const uint64_t at = memo_index_t(binom, loff, P.node_set[j]);
         plan[j] = mpdp_plan_node{P.node_l[j], P.node_r[j], P.node_set[j], (uint32_t)M.op[at], M.cost[at], M.card[at]};
     }
