@@ -31,6 +31,9 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
     if (t < kMaxRel) {
         L.adj[t] = 0;
         L.pbit[t] = 0;
+        L.lo1[t] = 0;
+        L.lorest[t] = 0;
+        L.sel1[t] = 1.0;
         L.desc[t] = 1u << t;
         L.card[t] = t < n ? C[t] : 1.0;
         if (t >= n) L.bcost[t] = 0.0;
@@ -54,6 +57,9 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
             const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
             if (hi == t) L.sel[start + (uint32_t)popc32(lower & ((1u << lo) - 1u))] = SL[e];
         }
+        L.lo1[t] = lower & (0u - lower);
+        L.lorest[t] = lower & ~(lower & (0u - lower));
+        L.sel1[t] = lower ? L.sel[start] : 1.0;  // written by this thread above
     }
     for (uint32_t i = t; i < 4 * 256; i += blockDim.x) {
         const uint32_t byte = i >> 8, x = i & 255u;

@@ -204,6 +204,7 @@ __device__ __forceinline__ void eval_vals(uint32_t A, uint32_t B, double cA, dou
 // that gathers a harmless singleton and offers nothing.
 template <int CM>
 __device__ __forceinline__ bool key_less_sel(unsigned long long ac, uint32_t al, uint32_t aop, const Key &b) {
+    if (CM == MPDP_COST_COUT) return (ac < b.c) | ((ac == b.c) & (al < b.l));
     return (ac < b.c) | ((ac == b.c) & ((al < b.l) | ((al == b.l) & (aop < b.op))));
 }
 
@@ -213,7 +214,7 @@ __device__ __forceinline__ void offer_if(bool on, Key &best, double cost, uint32
     const bool take = on & key_less_sel<CM>(c, left, op, best);
     best.c = take ? c : best.c;
     best.l = take ? left : best.l;
-    best.op = take ? op : best.op;
+    if (CM != MPDP_COST_COUT) best.op = take ? op : best.op;
 }
 
 template <int CM>
@@ -222,7 +223,11 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
                                               const double *__restrict__ card_km1) {
     constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 8 : 4;
     // one pass over S: its colex rank, the sum of C(s_i, i), and card(S) in
-    // card_of's order (members ascending, each card then its selectivities)
+    // card_of's order (members ascending, each card then the selectivities of
+    // its edges to smaller members, ascending).  The edge to v's lowest
+    // smaller neighbour comes from sel1 (times an exact 1.0 when that
+    // neighbour is outside S); v's other smaller neighbours in S, which a
+    // tree seldom has, go through the sel row.
     uint32_t rank = 0, bsum = 0;
     double c = 1.0;
     {
@@ -233,13 +238,20 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
             rank += L.binom[v * 33 + i + 1];
             bsum += L.binom[v * 33 + i];
             c = c * L.card[v];
-            const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
-            for (uint32_t U = lower & S; U; U &= U - 1)
-                c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+            c = c * ((S & L.lo1[v]) ? L.sel1[v] : 1.0);
+            const uint32_t rest = L.lorest[v] & S;
+            if (rest) {
+                const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+                for (uint32_t U = rest; U; U &= U - 1)
+                    c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+            }
         }
     }
     const double cardS = c < 1.0 ? 1.0 : c;
+    // C_out offers carry one operator, so the running best starts with it
+    // and the operator never decides
     Key best = worst_key();
+    if (CM == MPDP_COST_COUT) best.op = MPDP_OP_JOIN;
     uint32_t pa = 0, pb = 0, T = S;
     for (uint32_t i0 = 0; i0 < k; i0 += kPairBatch) {
         // members i0 .. i0 + kPairBatch - 1 (slots past k read relation

@@ -137,9 +137,14 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
     uint32_t at = 0;
     for (uint32_t v = 0; v < n; ++v) {
         L.selrow[v] = at;
-        for (uint32_t t = L.adj[v] & ((1u << v) - 1u); t; t &= t - 1)
+        const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+        L.lo1[v] = lower & (0u - lower);
+        L.lorest[v] = lower & ~L.lo1[v];
+        L.sel1[v] = lower ? g.sel_full[__builtin_ctz(lower) * 32 + v] : 1.0;
+        for (uint32_t t = lower; t; t &= t - 1)
             L.sel[at++] = g.sel_full[__builtin_ctz(t) * 32 + v];
     }
+    for (uint32_t v = n; v < 32; ++v) L.sel1[v] = 1.0;
     for (int b = 0; b < 4; ++b)
         for (uint32_t x = 0; x < 256; ++x) {
             uint32_t u = 0;

@@ -20,11 +20,14 @@ struct LdsImage {
     double card[kMaxRel];
     double bcost[kMaxRel];                    // cost of scanning relation v under the model
     double sel[kMaxRel * (kMaxRel - 1) / 2];  // per v: sel(u, v) of edges u < v, u ascending
+    double sel1[kMaxRel];                     // sel(lowest u < v adjacent to v, v); 1.0 without one
     uint32_t nb[4][256];                      // neighbours of a set, one table per bitmap byte
     uint32_t adj[kMaxRel];                    // bit u of adj[v]: edge (u, v)
     uint32_t pbit[kMaxRel];                   // tree joins rooted at 0: bit of the parent, 0 at the root
     uint32_t desc[kMaxRel];                   // tree joins: relations of the subtree rooted at v
     uint32_t selrow[kMaxRel];                 // first sel entry of relation v
+    uint32_t lo1[kMaxRel];                    // bit of the lowest neighbour u < v of v, 0 without one
+    uint32_t lorest[kMaxRel];                 // the other neighbours u < v of v
     uint32_t binom[33 * 33];                  // C(a, b) at [a * 33 + b]
     uint32_t pad[3];
 };
