@@ -93,6 +93,16 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
         }
     }
     __syncthreads();
+    if (Q.is_tree) {  // children of a set, one table per bitmap byte
+        for (uint32_t i = t; i < 4 * 256; i += blockDim.x) {
+            const uint32_t byte = i >> 8, x = i & 255u;
+            uint32_t c = 0;
+            for (uint32_t v = 1; v < n; ++v)
+                if (L.pbit[v] & (x << (8u * byte))) c |= 1u << v;
+            L.ch[byte][x] = c;
+        }
+        __syncthreads();
+    }
 }
 
 template <int CM>

@@ -50,6 +50,11 @@ __device__ __forceinline__ uint32_t grow(const uint32_t (*nb)[256], uint32_t sou
     return seen;
 }
 
+// Children of every relation in V, for a tree join rooted at relation 0.
+__device__ __forceinline__ uint32_t children(const uint32_t (*ch)[256], uint32_t V) {
+    return ch[0][V & 255u] | ch[1][(V >> 8) & 255u] | ch[2][(V >> 16) & 255u] | ch[3][V >> 24];
+}
+
 // Next bitmap with the same popcount (next k-subset in colex order).
 __device__ __forceinline__ uint32_t next_subset(uint32_t x) {
     const uint32_t r = x + lowbit(x);
@@ -692,7 +697,9 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         for (int j = 0; j < kTreeChunk; ++j) {
             sets[j] = S;
             if (r0 + (uint64_t)j < ncand) {
-                if (grow(L.nb, lowbit(S), S) == S) keep |= 1u << j;
+                // G[S] is a forest whose edges are the members with their
+                // parent in S; it is one tree when there are k - 1 of them
+                if ((uint32_t)popc32(S & children(L.ch, S)) == k - 1) keep |= 1u << j;
                 S = next_subset(S);
             }
         }

@@ -155,6 +155,14 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
                 }
             L.nb[b][x] = u;
         }
+    if (q.is_tree)
+        for (int b = 0; b < 4; ++b)
+            for (uint32_t x = 0; x < 256; ++x) {
+                uint32_t c = 0;
+                for (uint32_t v = 1; v < n; ++v)  // v's parent is the member of pbit[v]
+                    if (L.pbit[v] & (x << (8u * b))) c |= 1u << v;
+                L.ch[b][x] = c;
+            }
     for (uint32_t a = 0; a <= 32; ++a)
         for (uint32_t b = 0; b <= 32; ++b) L.binom[a * 33 + b] = (uint32_t)binom64(a, b);
     uint64_t off = 0;

@@ -22,6 +22,7 @@ struct LdsImage {
     double sel[kMaxRel * (kMaxRel - 1) / 2];  // per v: sel(u, v) of edges u < v, u ascending
     double sel1[kMaxRel];                     // sel(lowest u < v adjacent to v, v); 1.0 without one
     uint32_t nb[4][256];                      // neighbours of a set, one table per bitmap byte
+    uint32_t ch[4][256];                      // tree joins rooted at 0: children of a set, per byte
     uint32_t adj[kMaxRel];                    // bit u of adj[v]: edge (u, v)
     uint32_t pbit[kMaxRel];                   // tree joins rooted at 0: bit of the parent, 0 at the root
     uint32_t desc[kMaxRel];                   // tree joins: relations of the subtree rooted at v
