@@ -226,7 +226,7 @@ template <int CM>
 __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t k,
                                               uint64_t off_k, const double *__restrict__ cost_km1,
                                               const double *__restrict__ card_km1) {
-    constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 8 : 4;
+    constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 4 : 4;
     // one pass over S: its colex rank, the sum of C(s_i, i), and card(S) in
     // card_of's order (members ascending, each card then the selectivities of
     // its edges to smaller members, ascending).  The edge to v's lowest
