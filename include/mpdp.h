@@ -241,6 +241,84 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
                                 mpdp_batch_stats *stats_out);
 
 /*
+ * Schedule of one query in the batched kernel (defaults in brackets, which
+ * mpdp_optimize_batch uses):
+ *   tree_chunk    acyclic queries: consecutive colex ranks per lane in each
+ *                 level's fused unrank, filter and evaluate pass: 1, 2 or 4 [4]
+ *   heavy_chunks  cyclic queries: a set whose Alg. 3 candidates fill more
+ *                 than this many chunks of 16 is evaluated by the whole
+ *                 workgroup, a smaller one by one wave: 1 .. 65535 [256]
+ * Every schedule gives the same plans and costs; only the time differs.
+ */
+typedef struct { uint32_t tree_chunk, heavy_chunks; } mpdp_batch_schedule;
+
+/* mpdp_optimize_batch with a schedule per query: schedules is host memory,
+ * nq entries in input order, or NULL for the defaults.  MPDP_EINVAL for a
+ * schedule outside the ranges above; everything else as mpdp_optimize_batch. */
+mpdp_status mpdp_optimize_batch_sched(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                      const double *cardinalities, const double *selectivities,
+                                      mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes,
+                                      void *hip_stream, uint32_t flags, const mpdp_batch_schedule *schedules,
+                                      mpdp_plan_node *plans_out, double *costs_out, double *latency_us_out,
+                                      double *start_us_out, mpdp_batch_stats *stats_out);
+
+typedef struct {
+    uint32_t classes;       /* query classes tuned                                        */
+    uint32_t launches;      /* batch launches spent timing candidates                      */
+    double ms_total;        /* host wall time of the tuning                                */
+    double est_default_ms;  /* sum over queries of their class's median device time, defaults */
+    double est_tuned_ms;    /* the same with the chosen schedules                          */
+} mpdp_batch_tune_stats;
+
+/*
+ * Autotuner of the batched kernel's per-query schedule.  Queries fall into
+ * classes by (n, whether the join graph is a tree, edges beyond a spanning
+ * tree: 0, 1-2, 3-5, 6 or more).  Each candidate (tree_chunk 1, 2, 4;
+ * heavy_chunks 32, 64, 128, 256, 1024) runs over the whole batch `reps`
+ * times, acyclic and cyclic candidates sharing launches; every query's
+ * device time comes from the kernel's clock at its start and end, and each
+ * class gets the candidate with the smallest median time over its queries
+ * and repetitions (ties to the default).  schedules_out: host, nq entries in
+ * input order.  reps in 1..16; other arguments and errors as in
+ * mpdp_optimize_batch (the workspace is sized by mpdp_batch_workspace_bytes).
+ */
+mpdp_status mpdp_batch_autotune(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                                uint32_t reps, mpdp_batch_schedule *schedules_out,
+                                mpdp_batch_tune_stats *stats_out);
+
+/*
+ * A batch captured in a HIP graph: the upload of the query data, the
+ * persistent batched kernel and the downloads of plans, costs and clocks are
+ * recorded once for a fixed batch shape (every query's n and m, the cost
+ * model, the workspace) and replayed with new data by mpdp_batch_graph_run,
+ * so a serving loop issues one graph launch per batch.  The handle owns
+ * pinned host staging buffers (hipHostMalloc).  The workspace, sized by
+ * mpdp_batch_workspace_bytes, must outlive the handle and not be used by
+ * other calls meanwhile; replays of one handle must not overlap.
+ * mpdp_batch_graph_create returns MPDP_EINVAL for a bad shape or workspace
+ * and MPDP_EDEVICE if capture fails; *graph_out is NULL on error.
+ */
+typedef struct mpdp_batch_graph mpdp_batch_graph;
+
+mpdp_status mpdp_batch_graph_create(uint32_t nq, const mpdp_batch_query *queries, mpdp_cost_model cost_model,
+                                    void *d_workspace, size_t ws_bytes, mpdp_batch_graph **graph_out);
+
+/* One replay on hip_stream, waited for.  queries must have, query by query,
+ * the n and m given at creation (their offsets may differ); the data are
+ * validated as in mpdp_optimize_batch; schedules as in
+ * mpdp_optimize_batch_sched; outputs as in mpdp_optimize_batch. */
+mpdp_status mpdp_batch_graph_run(mpdp_batch_graph *graph, const mpdp_batch_query *queries,
+                                 const mpdp_edge *edges, const double *cardinalities,
+                                 const double *selectivities, const mpdp_batch_schedule *schedules,
+                                 void *hip_stream, mpdp_plan_node *plans_out, double *costs_out,
+                                 double *latency_us_out, mpdp_batch_stats *stats_out);
+
+/* Free the handle, its graph and its staging buffers (NULL is ignored). */
+void mpdp_batch_graph_destroy(mpdp_batch_graph *graph);
+
+/*
  * Large queries (Section 4): heuristics that hand sub-problems of at most k
  * units to the exact DP above, on the GPU.
  *   MPDP_LARGE_GOO      greedy operator ordering alone: join the two

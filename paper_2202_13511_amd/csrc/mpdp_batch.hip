@@ -163,8 +163,21 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
             if (Q.is_tree) {
                 if (t == 0) s_level = 0;
                 __syncthreads();
-                const uint32_t found =
-                    level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 255) / 256, rings[wave], lane);
+                uint32_t found;
+                switch (Q.sched & kSchedChunkMask) {  // consecutive ranks per lane
+                    case 0:
+                        found = level_tree_wave<CM, 1>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 63) / 64,
+                                                       rings[wave], lane);
+                        break;
+                    case 1:
+                        found = level_tree_wave<CM, 2>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 127) / 128,
+                                                       rings[wave], lane);
+                        break;
+                    default:
+                        found = level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 255) / 256,
+                                                       rings[wave], lane);
+                        break;
+                }
                 if (lane == 0 && found) atomicAdd(&s_level, found);
                 __syncthreads();
                 if (t == 0) {
@@ -182,7 +195,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
             const uint32_t count = s_ntree + s_ngen;
             // light work: tree-inducing sets one per lane, other sets one per wave
             light_sets<CM>(L, M, list, cap, s_ntree, s_ngen, wave, kBW, WS[wave], hv, &s_hcount, lane, my_ccp,
-                           my_eval);
+                           my_eval, false, (Q.sched >> kSchedHeavyShift) & 0xffffu);
             __syncthreads();
             // heavy sets: the whole workgroup each
             const uint32_t hcount = s_hcount;

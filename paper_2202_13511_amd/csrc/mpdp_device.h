@@ -803,7 +803,7 @@ template <int CM>
 __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *list, uint32_t cap, uint32_t ntree,
                            uint32_t ngen, uint32_t w0, uint32_t wstride, WaveScratch &W, uint32_t *heavy,
                            uint32_t *nheavy, uint32_t lane, unsigned long long &ccp, unsigned long long &evaluated,
-                           bool dpsub = false) {
+                           bool dpsub = false, uint32_t heavy_chunks = kHeavyChunks) {
     const uint32_t groups = (ntree + 63u) >> 6;
     for (uint32_t i = w0; i < groups + ngen; i += wstride) {
         if (i < groups) {
@@ -817,7 +817,7 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
         }
         const uint32_t S = list[cap - 1u - (i - groups)];
         const SetBlocks sb = dpsub ? whole_set(S, W, (int)lane, 64u) : analyze_set(L, S, W, (int)lane, 64u);
-        if (sb.chunks16 > kHeavyChunks) {
+        if (sb.chunks16 > heavy_chunks) {
             if (lane == 0) heavy[atomicAdd(nheavy, 1u)] = S;
             wave_sync_lds();
             continue;

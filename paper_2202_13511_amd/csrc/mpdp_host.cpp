@@ -369,13 +369,24 @@ mpdp_status validate_batch_query(const mpdp_batch_query &Q, const mpdp_edge *edg
     return seen == full ? MPDP_OK : MPDP_ENOTCONNECTED;
 }
 
-mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
-                       const double *cardinalities, const double *selectivities, const double *base_costs,
-                       mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
-                       uint32_t flags, mpdp_plan_node *plans_out, double *costs_out, double *latency_us_out,
-                       double *start_us_out, mpdp_batch_stats *stats_out) {
-    const double t0 = now_ms();
-    if (nq == 0 || !queries || !cardinalities || !plans_out || !costs_out) return MPDP_EINVAL;
+// Packed per-query schedule of the batched kernel (layout in mpdp_internal.h).
+bool encode_schedule(const mpdp_batch_schedule &sc, uint32_t &packed) {
+    uint32_t c;
+    switch (sc.tree_chunk) {
+        case 1: c = 0; break;
+        case 2: c = 1; break;
+        case 4: c = 2; break;
+        default: return false;
+    }
+    if (sc.heavy_chunks < 1 || sc.heavy_chunks > 0xffffu) return false;
+    packed = c | (sc.heavy_chunks << mpdp::kSchedHeavyShift);
+    return true;
+}
+
+mpdp_status check_batch_args(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                             const double *cardinalities, const double *selectivities, const double *base_costs,
+                             mpdp_cost_model cost_model, const mpdp_batch_schedule *sched) {
+    if (nq == 0 || !queries || !cardinalities) return MPDP_EINVAL;
     if (cost_model != MPDP_COST_COUT && cost_model != MPDP_COST_PGLIKE) return MPDP_EINVAL;
     uint64_t sum_m = 0;
     for (uint32_t i = 0; i < nq; ++i) sum_m += queries[i].m;
@@ -383,45 +394,52 @@ mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_
     for (uint32_t i = 0; i < nq; ++i) {
         const mpdp_status st = validate_batch_query(queries[i], edges, cardinalities, selectivities, base_costs);
         if (st != MPDP_OK) return st;
+        uint32_t packed;
+        if (sched && !encode_schedule(sched[i], packed)) return MPDP_EINVAL;
     }
-    BatchLayout B;
-    if (!batch_layout(nq, queries, B)) return MPDP_EINVAL;
-    if (!d_workspace) return MPDP_EINVAL;
-    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return MPDP_EINVAL;
-    if (ws_bytes < B.total) return MPDP_ENOMEM;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    char *base = static_cast<char *>(d_workspace);
+    return MPDP_OK;
+}
 
-    // one host image of everything the kernel reads, uploaded in one copy
-    std::vector<char> up(B.plans);
-    uint32_t *binom = reinterpret_cast<uint32_t *>(up.data() + B.binom);
-    for (uint32_t a = 0; a <= 32; ++a)
-        for (uint32_t b = 0; b <= 32; ++b) binom[a * 33 + b] = (uint32_t)binom64(a, b);
-    auto *bc = reinterpret_cast<mpdp::BatchCounters *>(up.data() + B.counters);
-    bc->next = 0;
-    bc->pad = 0;
-    bc->t0 = ~0ull;
-    auto *dq = reinterpret_cast<mpdp::BatchQueryDev *>(up.data() + B.queries);
-    uint32_t *de = reinterpret_cast<uint32_t *>(up.data() + B.edges);
-    double *dc = reinterpret_cast<double *>(up.data() + B.cards);
-    double *ds = reinterpret_cast<double *>(up.data() + B.sels);
-    double *db = reinterpret_cast<double *>(up.data() + B.bcosts);
-    // descriptors in the order the workgroups take them: larger queries first
-    std::vector<uint32_t> order(nq);
+// Order in which the workgroups take the queries (larger queries first, ties
+// in input order) and each query's first plan node in input order.
+void batch_order(uint32_t nq, const mpdp_batch_query *queries, std::vector<uint32_t> &order,
+                 std::vector<uint64_t> &plan_at) {
+    order.resize(nq);
     for (uint32_t i = 0; i < nq; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t a, uint32_t b) { return queries[a].n > queries[b].n; });
-    std::vector<uint64_t> plan_at(nq);
-    {
-        uint64_t p = 0;
-        for (uint32_t i = 0; i < nq; ++i) { plan_at[i] = p; p += 2ull * queries[i].n - 1; }
-    }
+    plan_at.resize(nq);
+    uint64_t p = 0;
+    for (uint32_t i = 0; i < nq; ++i) { plan_at[i] = p; p += 2ull * queries[i].n - 1; }
+}
+
+// Host image of everything the batched kernel reads (B.plans bytes), to be
+// uploaded to the workspace in one copy.
+void fill_batch_upload(char *up, const BatchLayout &B, uint32_t nq, const mpdp_batch_query *queries,
+                       const std::vector<uint32_t> &order, const std::vector<uint64_t> &plan_at,
+                       const mpdp_edge *edges, const double *cardinalities, const double *selectivities,
+                       const double *base_costs, mpdp_cost_model cost_model, const mpdp_batch_schedule *sched) {
+    std::memset(up, 0, B.plans);
+    uint32_t *binom = reinterpret_cast<uint32_t *>(up + B.binom);
+    for (uint32_t a = 0; a <= 32; ++a)
+        for (uint32_t b = 0; b <= 32; ++b) binom[a * 33 + b] = (uint32_t)binom64(a, b);
+    auto *bc = reinterpret_cast<mpdp::BatchCounters *>(up + B.counters);
+    bc->next = 0;
+    bc->pad = 0;
+    bc->t0 = ~0ull;
+    auto *dq = reinterpret_cast<mpdp::BatchQueryDev *>(up + B.queries);
+    uint32_t *de = reinterpret_cast<uint32_t *>(up + B.edges);
+    double *dc = reinterpret_cast<double *>(up + B.cards);
+    double *ds = reinterpret_cast<double *>(up + B.sels);
+    double *db = reinterpret_cast<double *>(up + B.bcosts);
     uint64_t eo = 0, co = 0;
     for (uint32_t j = 0; j < nq; ++j) {
         const uint32_t i = order[j];
         const mpdp_batch_query &Q = queries[i];
-        const uint64_t po = plan_at[i];
-        dq[j] = mpdp::BatchQueryDev{Q.n, Q.m, Q.m == Q.n - 1 ? 1u : 0u, (uint32_t)cost_model, co, eo, po};
+        uint32_t packed = mpdp::kSchedDefault;
+        if (sched) (void)encode_schedule(sched[i], packed);  // checked by check_batch_args
+        dq[j] = mpdp::BatchQueryDev{Q.n, Q.m, Q.m == Q.n - 1 ? 1u : 0u, (uint32_t)cost_model, co, eo, plan_at[i],
+                                    packed, 0u};
         for (uint32_t v = 0; v < Q.n; ++v) {
             dc[co + v] = cardinalities[Q.card_offset + v];
             db[co + v] = base_costs ? base_costs[Q.card_offset + v] : 0.0;
@@ -434,30 +452,24 @@ mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_
         co += Q.n;
         eo += Q.m;
     }
-    int dev = 0, rate_khz = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
-    const bool timing = (flags & MPDP_FLAG_TIMING) != 0;
-    EventPool ev;
-    if (timing) HIPCHK(ev.make(2));
-    HIPCHK(hipMemcpyAsync(base, up.data(), up.size(), hipMemcpyHostToDevice, s));
-    if (timing) HIPCHK(hipEventRecord(ev.ev[0], s));
-    HIPCHK(mpdp::launch_batch(cost_model, B.workgroups, reinterpret_cast<mpdp::BatchQueryDev *>(base + B.queries),
+}
+
+hipError_t enqueue_batch_kernel(char *base, const BatchLayout &B, uint32_t nq, mpdp_cost_model cost_model,
+                                bool with_bcosts, hipStream_t s) {
+    return mpdp::launch_batch(cost_model, B.workgroups, reinterpret_cast<mpdp::BatchQueryDev *>(base + B.queries),
                               nq, reinterpret_cast<uint32_t *>(base + B.edges),
                               reinterpret_cast<double *>(base + B.cards), reinterpret_cast<double *>(base + B.sels),
-                              base_costs ? reinterpret_cast<double *>(base + B.bcosts) : nullptr,
+                              with_bcosts ? reinterpret_cast<double *>(base + B.bcosts) : nullptr,
                               reinterpret_cast<uint32_t *>(base + B.binom), base + B.slots, B.slot_bytes, B.maxn,
                               reinterpret_cast<mpdp_plan_node *>(base + B.plans),
                               reinterpret_cast<mpdp::BatchOut *>(base + B.out),
-                              reinterpret_cast<mpdp::BatchCounters *>(base + B.counters), s));
-    if (timing) HIPCHK(hipEventRecord(ev.ev[1], s));
-    std::vector<mpdp::BatchOut> outs(nq);
-    mpdp::BatchCounters hbc{};
-    HIPCHK(hipMemcpyAsync(plans_out, base + B.plans, sizeof(mpdp_plan_node) * B.sum_nodes, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(outs.data(), base + B.out, sizeof(mpdp::BatchOut) * nq, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&hbc, base + B.counters, sizeof(hbc), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    mpdp_batch_stats st{};
+                              reinterpret_cast<mpdp::BatchCounters *>(base + B.counters), s);
+}
+
+// Per-query results from the downloaded outputs (outs in workgroup order).
+mpdp_status unpack_batch(uint32_t nq, const std::vector<uint32_t> &order, const mpdp::BatchOut *outs,
+                         const mpdp::BatchCounters &hbc, int rate_khz, double *costs_out, double *latency_us_out,
+                         double *start_us_out, mpdp_batch_stats *st) {
     const double us_per_tick = rate_khz > 0 ? 1e3 / (double)rate_khz : 0.0;
     for (uint32_t j = 0; j < nq; ++j) {
         const mpdp::BatchOut &o = outs[j];
@@ -466,10 +478,62 @@ mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_
         costs_out[i] = o.cost;
         if (latency_us_out) latency_us_out[i] = (double)(o.t_end - hbc.t0) * us_per_tick;
         if (start_us_out) start_us_out[i] = (double)(o.t_start - hbc.t0) * us_per_tick;
-        st.connected_sets += o.connected;
-        st.ccp_pairs += o.ccp;
-        st.evaluated_pairs += o.evaluated;
+        st->connected_sets += o.connected;
+        st->ccp_pairs += o.ccp;
+        st->evaluated_pairs += o.evaluated;
     }
+    return MPDP_OK;
+}
+
+int wall_clock_khz() {
+    int dev = 0, rate_khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return rate_khz;
+}
+
+mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                       const double *cardinalities, const double *selectivities, const double *base_costs,
+                       mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                       uint32_t flags, const mpdp_batch_schedule *sched, mpdp_plan_node *plans_out,
+                       double *costs_out, double *latency_us_out, double *start_us_out,
+                       mpdp_batch_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!plans_out || !costs_out) return MPDP_EINVAL;
+    mpdp_status st0 = check_batch_args(nq, queries, edges, cardinalities, selectivities, base_costs, cost_model,
+                                       sched);
+    if (st0 != MPDP_OK) return st0;
+    BatchLayout B;
+    if (!batch_layout(nq, queries, B)) return MPDP_EINVAL;
+    if (!d_workspace) return MPDP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return MPDP_EINVAL;
+    if (ws_bytes < B.total) return MPDP_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    char *base = static_cast<char *>(d_workspace);
+    std::vector<uint32_t> order;
+    std::vector<uint64_t> plan_at;
+    batch_order(nq, queries, order, plan_at);
+    std::vector<char> up(B.plans);
+    fill_batch_upload(up.data(), B, nq, queries, order, plan_at, edges, cardinalities, selectivities, base_costs,
+                      cost_model, sched);
+    const int rate_khz = wall_clock_khz();
+    const bool timing = (flags & MPDP_FLAG_TIMING) != 0;
+    EventPool ev;
+    if (timing) HIPCHK(ev.make(2));
+    HIPCHK(hipMemcpyAsync(base, up.data(), up.size(), hipMemcpyHostToDevice, s));
+    if (timing) HIPCHK(hipEventRecord(ev.ev[0], s));
+    HIPCHK(enqueue_batch_kernel(base, B, nq, cost_model, base_costs != nullptr, s));
+    if (timing) HIPCHK(hipEventRecord(ev.ev[1], s));
+    std::vector<mpdp::BatchOut> outs(nq);
+    mpdp::BatchCounters hbc{};
+    HIPCHK(hipMemcpyAsync(plans_out, base + B.plans, sizeof(mpdp_plan_node) * B.sum_nodes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(outs.data(), base + B.out, sizeof(mpdp::BatchOut) * nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hbc, base + B.counters, sizeof(hbc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    mpdp_batch_stats st{};
+    const mpdp_status ust = unpack_batch(nq, order, outs.data(), hbc, rate_khz, costs_out, latency_us_out,
+                                         start_us_out, &st);
+    if (ust != MPDP_OK) return ust;
     if (stats_out) {
         if (timing) {
             float ms = 0.f;
@@ -481,6 +545,157 @@ mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_
         st.ms_total = now_ms() - t0;
         *stats_out = st;
     }
+    return MPDP_OK;
+}
+
+// ---------------------------------------------------------------- batch schedule autotuner
+
+// Class of a query for the autotuner: n, acyclic or not, band of the number
+// of edges beyond a spanning tree.
+uint32_t tune_class(const mpdp_batch_query &Q) {
+    const uint32_t extra = Q.m - (Q.n - 1);  // the join graph is connected: m >= n - 1
+    const uint32_t band = extra == 0 ? 0u : (extra <= 2 ? 1u : (extra <= 5 ? 2u : 3u));
+    return (Q.n << 2) | band;
+}
+
+mpdp_status batch_autotune(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                           const double *card, const double *sel, mpdp_cost_model cm, void *d_ws, size_t ws_bytes,
+                           void *stream, uint32_t reps, mpdp_batch_schedule *out, mpdp_batch_tune_stats *stats) {
+    const double t0 = now_ms();
+    if (!out || reps < 1 || reps > 16) return MPDP_EINVAL;
+    mpdp_status st = check_batch_args(nq, queries, edges, card, sel, nullptr, cm, nullptr);
+    if (st != MPDP_OK) return st;
+    static const uint32_t kTreeCand[] = {4, 2, 1};              // default first
+    static const uint32_t kHeavyCand[] = {256, 32, 64, 128, 1024};
+    constexpr uint32_t nT = 3, nH = 5, nRuns = 5;
+    const mpdp_batch_schedule dflt{4, 256};
+    std::vector<uint64_t> nodes(1, 0);
+    for (uint32_t i = 0; i < nq; ++i) nodes[0] += 2ull * queries[i].n - 1;
+    std::vector<mpdp_plan_node> plans(nodes[0]);
+    std::vector<double> costs(nq), lat(nq), start(nq);
+    std::vector<mpdp_batch_schedule> sc(nq);
+    // times[i][c]: device times of query i under its candidate c
+    std::vector<std::vector<double>> times((size_t)nq * 5);
+    uint32_t launches = 0;
+    for (uint32_t r = 0; r < reps; ++r)
+        for (uint32_t run = 0; run < nRuns; ++run) {
+            for (uint32_t i = 0; i < nq; ++i) {
+                const bool tree = queries[i].m == queries[i].n - 1;
+                sc[i] = dflt;
+                if (tree) sc[i].tree_chunk = kTreeCand[run < nT ? run : 0];
+                else sc[i].heavy_chunks = kHeavyCand[run < nH ? run : 0];
+            }
+            st = batch_core(nq, queries, edges, card, sel, nullptr, cm, d_ws, ws_bytes, stream, 0, sc.data(),
+                            plans.data(), costs.data(), lat.data(), start.data(), nullptr);
+            if (st != MPDP_OK) return st;
+            ++launches;
+            for (uint32_t i = 0; i < nq; ++i) {
+                const bool tree = queries[i].m == queries[i].n - 1;
+                if (tree ? run >= nT : run >= nH) continue;
+                times[(size_t)i * 5 + run].push_back(lat[i] - start[i]);
+            }
+        }
+    // per class and candidate: median over the class's queries and repetitions
+    std::vector<uint32_t> cls(nq);
+    std::vector<uint32_t> keys;
+    for (uint32_t i = 0; i < nq; ++i) {
+        cls[i] = tune_class(queries[i]);
+        keys.push_back(cls[i]);
+    }
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    double est_default = 0.0, est_tuned = 0.0;
+    for (uint32_t key : keys) {
+        std::vector<uint32_t> members;
+        for (uint32_t i = 0; i < nq; ++i)
+            if (cls[i] == key) members.push_back(i);
+        const bool tree = queries[members[0]].m == queries[members[0]].n - 1;
+        const uint32_t ncand = tree ? nT : nH;
+        double med[5] = {0, 0, 0, 0, 0};
+        for (uint32_t c = 0; c < ncand; ++c) {
+            std::vector<double> v;
+            for (uint32_t i : members) v.insert(v.end(), times[(size_t)i * 5 + c].begin(), times[(size_t)i * 5 + c].end());
+            std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+            med[c] = v[v.size() / 2];
+        }
+        uint32_t best = 0;  // candidate 0 is the default; a later one must be strictly faster
+        for (uint32_t c = 1; c < ncand; ++c)
+            if (med[c] < med[best]) best = c;
+        for (uint32_t i : members) {
+            out[i] = dflt;
+            if (tree) out[i].tree_chunk = kTreeCand[best];
+            else out[i].heavy_chunks = kHeavyCand[best];
+        }
+        est_default += med[0] * (double)members.size() * 1e-3;
+        est_tuned += med[best] * (double)members.size() * 1e-3;
+    }
+    if (stats) {
+        stats->classes = (uint32_t)keys.size();
+        stats->launches = launches;
+        stats->est_default_ms = est_default;
+        stats->est_tuned_ms = est_tuned;
+        stats->ms_total = now_ms() - t0;
+    }
+    return MPDP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- batch captured in a HIP graph
+
+struct mpdp_batch_graph {
+    uint32_t nq = 0;
+    mpdp_cost_model cm = MPDP_COST_COUT;
+    std::vector<mpdp_batch_query> shape;  // n and m per query, offsets as given at creation
+    BatchLayout B{};
+    std::vector<uint32_t> order;
+    std::vector<uint64_t> plan_at;
+    char *base = nullptr;                 // device workspace
+    char *h_up = nullptr;                 // pinned: the upload image (B.plans bytes)
+    mpdp_plan_node *h_plans = nullptr;    // pinned downloads
+    mpdp::BatchOut *h_out = nullptr;
+    mpdp::BatchCounters *h_bc = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int rate_khz = 0;
+};
+
+namespace {
+
+void release_batch_graph(mpdp_batch_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->h_up) (void)hipHostFree(g->h_up);
+    if (g->h_plans) (void)hipHostFree(g->h_plans);
+    if (g->h_out) (void)hipHostFree(g->h_out);
+    if (g->h_bc) (void)hipHostFree(g->h_bc);
+    delete g;
+}
+
+// Record upload, kernel and downloads on a capture stream of our own (the
+// caller's stream may be the legacy default stream, which cannot capture).
+mpdp_status capture_batch_graph(mpdp_batch_graph *g) {
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        ok = hipMemcpyAsync(g->base, g->h_up, g->B.plans, hipMemcpyHostToDevice, cs) == hipSuccess &&
+             enqueue_batch_kernel(g->base, g->B, g->nq, g->cm, false, cs) == hipSuccess &&
+             hipMemcpyAsync(g->h_plans, g->base + g->B.plans, sizeof(mpdp_plan_node) * g->B.sum_nodes,
+                            hipMemcpyDeviceToHost, cs) == hipSuccess &&
+             hipMemcpyAsync(g->h_out, g->base + g->B.out, sizeof(mpdp::BatchOut) * g->nq, hipMemcpyDeviceToHost,
+                            cs) == hipSuccess &&
+             hipMemcpyAsync(g->h_bc, g->base + g->B.counters, sizeof(mpdp::BatchCounters), hipMemcpyDeviceToHost,
+                            cs) == hipSuccess;
+        hipGraph_t graph = nullptr;
+        const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
+        ok = ok && ended && graph;
+        if (graph) g->graph = graph;
+    }
+    (void)hipStreamDestroy(cs);
+    if (!ok) return MPDP_EDEVICE;
+    HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     return MPDP_OK;
 }
 
@@ -512,8 +727,8 @@ mpdp_status optimize_units_batch(uint32_t nq, const mpdp_batch_query *queries, c
                                  const double *card, const double *sel, const double *base_costs,
                                  mpdp_cost_model cm, void *d_ws, size_t ws_bytes, hipStream_t s,
                                  mpdp_plan_node *plans_out, double *costs_out) {
-    return batch_core(nq, queries, edges, card, sel, base_costs, cm, d_ws, ws_bytes, s, 0, plans_out, costs_out,
-                      nullptr, nullptr, nullptr);
+    return batch_core(nq, queries, edges, card, sel, base_costs, cm, d_ws, ws_bytes, s, 0, nullptr, plans_out,
+                      costs_out, nullptr, nullptr, nullptr);
 }
 
 }  // namespace mpdp_host
@@ -531,8 +746,110 @@ mpdp_status mpdp_optimize_batch(uint32_t nq, const mpdp_batch_query *queries, co
                                 uint32_t flags, mpdp_plan_node *plans_out, double *costs_out,
                                 double *latency_us_out, double *start_us_out, mpdp_batch_stats *stats_out) {
     return batch_core(nq, queries, edges, cardinalities, selectivities, nullptr, cost_model, d_workspace, ws_bytes,
-                      hip_stream, flags, plans_out, costs_out, latency_us_out, start_us_out, stats_out);
+                      hip_stream, flags, nullptr, plans_out, costs_out, latency_us_out, start_us_out, stats_out);
 }
+
+mpdp_status mpdp_optimize_batch_sched(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                      const double *cardinalities, const double *selectivities,
+                                      mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes,
+                                      void *hip_stream, uint32_t flags, const mpdp_batch_schedule *schedules,
+                                      mpdp_plan_node *plans_out, double *costs_out, double *latency_us_out,
+                                      double *start_us_out, mpdp_batch_stats *stats_out) {
+    return batch_core(nq, queries, edges, cardinalities, selectivities, nullptr, cost_model, d_workspace, ws_bytes,
+                      hip_stream, flags, schedules, plans_out, costs_out, latency_us_out, start_us_out, stats_out);
+}
+
+mpdp_status mpdp_batch_autotune(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                const double *cardinalities, const double *selectivities,
+                                mpdp_cost_model cost_model, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                                uint32_t reps, mpdp_batch_schedule *schedules_out,
+                                mpdp_batch_tune_stats *stats_out) {
+    return batch_autotune(nq, queries, edges, cardinalities, selectivities, cost_model, d_workspace, ws_bytes,
+                          hip_stream, reps, schedules_out, stats_out);
+}
+
+mpdp_status mpdp_batch_graph_create(uint32_t nq, const mpdp_batch_query *queries, mpdp_cost_model cost_model,
+                                    void *d_workspace, size_t ws_bytes, mpdp_batch_graph **graph_out) {
+    if (!graph_out) return MPDP_EINVAL;
+    *graph_out = nullptr;
+    if (nq == 0 || !queries) return MPDP_EINVAL;
+    if (cost_model != MPDP_COST_COUT && cost_model != MPDP_COST_PGLIKE) return MPDP_EINVAL;
+    for (uint32_t i = 0; i < nq; ++i) {
+        const mpdp_batch_query &Q = queries[i];
+        if (Q.n == 0) return MPDP_EINVAL;
+        if (Q.n > mpdp::kBatchMaxRel) return MPDP_ETOOLARGE;
+        if (Q.m + 1 < Q.n || Q.m > Q.n * (Q.n - 1) / 2) return MPDP_EINVAL;
+    }
+    auto *g = new mpdp_batch_graph;
+    g->nq = nq;
+    g->cm = cost_model;
+    g->shape.assign(queries, queries + nq);
+    if (!batch_layout(nq, queries, g->B) || !d_workspace ||
+        reinterpret_cast<uintptr_t>(d_workspace) % kAlign) {
+        release_batch_graph(g);
+        return MPDP_EINVAL;
+    }
+    if (ws_bytes < g->B.total) {
+        release_batch_graph(g);
+        return MPDP_ENOMEM;
+    }
+    g->base = static_cast<char *>(d_workspace);
+    batch_order(nq, queries, g->order, g->plan_at);
+    g->rate_khz = wall_clock_khz();
+    const bool ok =
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_up), g->B.plans, hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_plans), sizeof(mpdp_plan_node) * g->B.sum_nodes,
+                      hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_out), sizeof(mpdp::BatchOut) * nq, hipHostMallocDefault) ==
+            hipSuccess &&
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_bc), sizeof(mpdp::BatchCounters), hipHostMallocDefault) ==
+            hipSuccess;
+    if (!ok) {
+        release_batch_graph(g);
+        return MPDP_ENOMEM;
+    }
+    std::memset(g->h_up, 0, g->B.plans);
+    const mpdp_status st = capture_batch_graph(g);
+    if (st != MPDP_OK) {
+        release_batch_graph(g);
+        return st;
+    }
+    *graph_out = g;
+    return MPDP_OK;
+}
+
+mpdp_status mpdp_batch_graph_run(mpdp_batch_graph *g, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                                 const double *cardinalities, const double *selectivities,
+                                 const mpdp_batch_schedule *schedules, void *hip_stream,
+                                 mpdp_plan_node *plans_out, double *costs_out, double *latency_us_out,
+                                 mpdp_batch_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!g || !queries || !plans_out || !costs_out) return MPDP_EINVAL;
+    for (uint32_t i = 0; i < g->nq; ++i)
+        if (queries[i].n != g->shape[i].n || queries[i].m != g->shape[i].m) return MPDP_EINVAL;
+    const mpdp_status st0 = check_batch_args(g->nq, queries, edges, cardinalities, selectivities, nullptr, g->cm,
+                                             schedules);
+    if (st0 != MPDP_OK) return st0;
+    fill_batch_upload(g->h_up, g->B, g->nq, queries, g->order, g->plan_at, edges, cardinalities, selectivities,
+                      nullptr, g->cm, schedules);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipGraphLaunch(g->exec, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(plans_out, g->h_plans, sizeof(mpdp_plan_node) * g->B.sum_nodes);
+    mpdp_batch_stats st{};
+    const mpdp_status ust = unpack_batch(g->nq, g->order, g->h_out, *g->h_bc, g->rate_khz, costs_out,
+                                         latency_us_out, nullptr, &st);
+    if (ust != MPDP_OK) return ust;
+    if (stats_out) {
+        st.workgroups = g->B.workgroups;
+        st.max_n = g->B.maxn;
+        st.ms_total = now_ms() - t0;
+        *stats_out = st;
+    }
+    return MPDP_OK;
+}
+
+void mpdp_batch_graph_destroy(mpdp_batch_graph *graph) { release_batch_graph(graph); }
 
 const char *mpdp_status_str(mpdp_status s) {
     switch (s) {

@@ -68,7 +68,16 @@ struct Counters {
 struct BatchQueryDev {
     uint32_t n, m, is_tree, cost_model;
     uint64_t card_off, edge_off, plan_off;
+    uint32_t sched, pad;  // the query's schedule, packed as below
 };
+
+// Schedule of one query in the batched kernel: bits 0-1 hold log2 of the
+// consecutive ranks per lane of a tree query's levels (1, 2 or 4), bits
+// 8-23 the number of 16-candidate chunks above which a set of a cyclic
+// query is evaluated by the whole workgroup instead of one wave.
+constexpr uint32_t kSchedChunkMask = 3u;
+constexpr uint32_t kSchedHeavyShift = 8;
+constexpr uint32_t kSchedDefault = 2u | (256u << kSchedHeavyShift);
 
 struct BatchOut {
     double cost;

@@ -26,6 +26,8 @@ _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
             "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_optimize_cpu", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
+            "mpdp_optimize_batch_sched", "mpdp_batch_autotune", "mpdp_batch_graph_create", "mpdp_batch_graph_run",
+            "mpdp_batch_graph_destroy",
             "mpdp_optimize_large", "mpdp_large_examples", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
             "mpdp_scorer_load", "mpdp_scorer_forward", "mpdp_scorer_grad", "mpdp_scorer_train_step"]
 SCORER_IN, SCORER_HIDDEN = 32, 256
@@ -52,6 +54,15 @@ class mpdp_stats(ctypes.Structure):
 class mpdp_batch_query(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("card_offset", ctypes.c_uint32),
                 ("edge_offset", ctypes.c_uint32)]
+
+
+class mpdp_batch_schedule(ctypes.Structure):
+    _fields_ = [("tree_chunk", ctypes.c_uint32), ("heavy_chunks", ctypes.c_uint32)]
+
+
+class mpdp_batch_tune_stats(ctypes.Structure):
+    _fields_ = [("classes", ctypes.c_uint32), ("launches", ctypes.c_uint32), ("ms_total", ctypes.c_double),
+                ("est_default_ms", ctypes.c_double), ("est_tuned_ms", ctypes.c_double)]
 
 
 class mpdp_batch_stats(ctypes.Structure):
@@ -142,6 +153,21 @@ def load(path: str = LIB_PATH):
                                       u32, ctypes.POINTER(mpdp_plan_node), f64p, f64p, f64p,
                                       ctypes.POINTER(mpdp_batch_stats)]
     L.mpdp_optimize_batch.restype = ctypes.c_int
+    sch = ctypes.POINTER(mpdp_batch_schedule)
+    L.mpdp_optimize_batch_sched.argtypes = [u32, bq, ctypes.POINTER(mpdp_edge), f64p, f64p, ctypes.c_int, vp, sz, vp,
+                                            u32, sch, ctypes.POINTER(mpdp_plan_node), f64p, f64p, f64p,
+                                            ctypes.POINTER(mpdp_batch_stats)]
+    L.mpdp_optimize_batch_sched.restype = ctypes.c_int
+    L.mpdp_batch_autotune.argtypes = [u32, bq, ctypes.POINTER(mpdp_edge), f64p, f64p, ctypes.c_int, vp, sz, vp, u32,
+                                      sch, ctypes.POINTER(mpdp_batch_tune_stats)]
+    L.mpdp_batch_autotune.restype = ctypes.c_int
+    L.mpdp_batch_graph_create.argtypes = [u32, bq, ctypes.c_int, vp, sz, ctypes.POINTER(vp)]
+    L.mpdp_batch_graph_create.restype = ctypes.c_int
+    L.mpdp_batch_graph_run.argtypes = [vp, bq, ctypes.POINTER(mpdp_edge), f64p, f64p, sch, vp,
+                                       ctypes.POINTER(mpdp_plan_node), f64p, f64p, ctypes.POINTER(mpdp_batch_stats)]
+    L.mpdp_batch_graph_run.restype = ctypes.c_int
+    L.mpdp_batch_graph_destroy.argtypes = [vp]
+    L.mpdp_batch_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -391,8 +417,29 @@ def batch_workspace(queries, device="cuda"):
     return torch.empty(max(mpdp_batch_workspace_bytes(queries), 256), dtype=torch.uint8, device=device)
 
 
-def mpdp_optimize_batch(queries, cost_model: int, ws, stream=None, flags: int = 0) -> BatchResult:
-    """All queries (n <= 20 each) in one persistent launch."""
+def _split_plans(queries, plans):
+    out, at = [], 0
+    for q in queries:
+        k = 2 * q.n - 1
+        out.append([dict(left=p.left, right=p.right, relset=p.relset, op=p.op, cost=p.cost, card=p.card)
+                    for p in plans[at: at + k]])
+        at += k
+    return out
+
+
+def _schedules(queries, schedules):
+    """None, or one (tree_chunk, heavy_chunks) pair per query."""
+    if schedules is None:
+        return None
+    arr = (mpdp_batch_schedule * len(queries))()
+    for i, (tc, hc) in enumerate(schedules):
+        arr[i] = mpdp_batch_schedule(int(tc), int(hc))
+    return arr
+
+
+def mpdp_optimize_batch(queries, cost_model: int, ws, stream=None, flags: int = 0, schedules=None) -> BatchResult:
+    """All queries (n <= 20 each) in one persistent launch; `schedules`, if
+    given, holds one (tree_chunk, heavy_chunks) pair per query."""
     import torch
     qs, c, e, s = _batch_marshal(queries)
     if stream is None:
@@ -404,21 +451,89 @@ def mpdp_optimize_batch(queries, cost_model: int, ws, stream=None, flags: int = 
     start = np.zeros(len(queries), np.float64)
     st = mpdp_batch_stats()
     f64p = ctypes.POINTER(ctypes.c_double)
-    rc = load().mpdp_optimize_batch(len(queries), qs, e.ctypes.data_as(ctypes.POINTER(mpdp_edge)),
-                                    c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), int(cost_model),
-                                    ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                                    ctypes.c_void_p(stream.cuda_stream), int(flags), plans,
-                                    costs.ctypes.data_as(f64p), lat.ctypes.data_as(f64p),
-                                    start.ctypes.data_as(f64p), ctypes.byref(st))
+    args = [len(queries), qs, e.ctypes.data_as(ctypes.POINTER(mpdp_edge)), c.ctypes.data_as(f64p),
+            s.ctypes.data_as(f64p), int(cost_model), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+            ctypes.c_void_p(stream.cuda_stream), int(flags)]
+    tail = [plans, costs.ctypes.data_as(f64p), lat.ctypes.data_as(f64p), start.ctypes.data_as(f64p), ctypes.byref(st)]
+    sch = _schedules(queries, schedules)
+    if sch is None:
+        rc = load().mpdp_optimize_batch(*args, *tail)
+    else:
+        rc = load().mpdp_optimize_batch_sched(*args, sch, *tail)
     if rc != MPDP_OK:
         raise MpdpError(rc, mpdp_status_str(rc))
-    out, at = [], 0
-    for q in queries:
-        k = 2 * q.n - 1
-        out.append([dict(left=p.left, right=p.right, relset=p.relset, op=p.op, cost=p.cost, card=p.card)
-                    for p in plans[at: at + k]])
-        at += k
-    return BatchResult(costs.tolist(), out, lat, {f: getattr(st, f) for f, _ in mpdp_batch_stats._fields_}, start)
+    return BatchResult(costs.tolist(), _split_plans(queries, plans), lat,
+                       {f: getattr(st, f) for f, _ in mpdp_batch_stats._fields_}, start)
+
+
+def mpdp_batch_autotune(queries, cost_model: int, ws, reps: int = 2, stream=None):
+    """Per-query schedules chosen by the library's autotuner: returns
+    ([(tree_chunk, heavy_chunks)] per query, stats dict)."""
+    import torch
+    qs, c, e, s = _batch_marshal(queries)
+    if stream is None:
+        stream = torch.cuda.current_stream(ws.device)
+    out = (mpdp_batch_schedule * len(queries))()
+    st = mpdp_batch_tune_stats()
+    f64p = ctypes.POINTER(ctypes.c_double)
+    rc = load().mpdp_batch_autotune(len(queries), qs, e.ctypes.data_as(ctypes.POINTER(mpdp_edge)),
+                                    c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), int(cost_model),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                    ctypes.c_void_p(stream.cuda_stream), int(reps), out, ctypes.byref(st))
+    if rc != MPDP_OK:
+        raise MpdpError(rc, mpdp_status_str(rc))
+    return ([(o.tree_chunk, o.heavy_chunks) for o in out],
+            {f: getattr(st, f) for f, _ in mpdp_batch_tune_stats._fields_})
+
+
+class BatchGraph:
+    """A batch shape captured once in a HIP graph (mpdp_batch_graph_*) and
+    replayed with the data of any batch of that shape."""
+
+    def __init__(self, queries, cost_model: int, ws):
+        qs, _, _, _ = _batch_marshal(queries)
+        self.shape = [(q.n, q.m) for q in queries]
+        self.cost_model = int(cost_model)
+        self.ws = ws  # the workspace must outlive the graph
+        h = ctypes.c_void_p()
+        rc = load().mpdp_batch_graph_create(len(queries), qs, self.cost_model, ctypes.c_void_p(ws.data_ptr()),
+                                            ws.numel() * ws.element_size(), ctypes.byref(h))
+        if rc != MPDP_OK:
+            raise MpdpError(rc, mpdp_status_str(rc))
+        self.handle = h
+
+    def run(self, queries, schedules=None, stream=None) -> BatchResult:
+        import torch
+        if self.handle is None:
+            raise MpdpError(MPDP_EINVAL, "graph destroyed")
+        qs, c, e, s = _batch_marshal(queries)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.ws.device)
+        total = sum(2 * q.n - 1 for q in queries)
+        plans = (mpdp_plan_node * total)()
+        costs = np.zeros(len(queries), np.float64)
+        lat = np.zeros(len(queries), np.float64)
+        st = mpdp_batch_stats()
+        f64p = ctypes.POINTER(ctypes.c_double)
+        rc = load().mpdp_batch_graph_run(self.handle, qs, e.ctypes.data_as(ctypes.POINTER(mpdp_edge)),
+                                         c.ctypes.data_as(f64p), s.ctypes.data_as(f64p),
+                                         _schedules(queries, schedules), ctypes.c_void_p(stream.cuda_stream), plans,
+                                         costs.ctypes.data_as(f64p), lat.ctypes.data_as(f64p), ctypes.byref(st))
+        if rc != MPDP_OK:
+            raise MpdpError(rc, mpdp_status_str(rc))
+        return BatchResult(costs.tolist(), _split_plans(queries, plans), lat,
+                           {f: getattr(st, f) for f, _ in mpdp_batch_stats._fields_})
+
+    def close(self):
+        if self.handle is not None:
+            load().mpdp_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- learned scorer (mpdp_scorer.h)

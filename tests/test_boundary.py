@@ -130,3 +130,46 @@ def test_batch_validation_without_gpu():
     disc = W.Query(4, np.array([[0, 1], [2, 3]], np.uint32), np.full(4, 10.0), np.full(2, 0.5))
     assert status([disc]) == mpdp.MPDP_ENOTCONNECTED
     assert status(good) == mpdp.MPDP_EINVAL  # valid queries, but no workspace
+
+
+def test_batch_schedule_tuner_and_graph_validation_without_gpu():
+    """The scheduled batch call, the autotuner and the graph handle reject
+    bad arguments on the host, before any HIP call."""
+    lib = mpdp.load()
+    import torch  # noqa: F401
+    good = [W.chain(5, 0), W.star(6, 1), W.cycle_chords(4, n=7, chords=1)]
+    qs, c, e, s = mpdp._batch_marshal(good)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    ep = e.ctypes.data_as(ctypes.POINTER(mpdp.mpdp_edge))
+    plans = (mpdp.mpdp_plan_node * sum(2 * q.n - 1 for q in good))()
+    costs = np.zeros(len(good))
+
+    def sched_status(pairs):
+        sch = mpdp._schedules(good, pairs)
+        return lib.mpdp_optimize_batch_sched(len(good), qs, ep, c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), 0,
+                                             None, 0, None, 0, sch, plans, costs.ctypes.data_as(f64p), None, None,
+                                             None)
+
+    for bad in ((3, 256), (0, 256), (8, 256), (4, 0), (4, 65536)):
+        assert sched_status([bad] * 3) == mpdp.MPDP_EINVAL, bad
+    # valid schedules pass validation and then stop at the missing workspace
+    assert sched_status([(1, 1), (2, 65535), (4, 256)]) == mpdp.MPDP_EINVAL
+
+    out = (mpdp.mpdp_batch_schedule * len(good))()
+    st = mpdp.mpdp_batch_tune_stats()
+    for reps, o in ((0, out), (17, out), (2, None)):
+        assert lib.mpdp_batch_autotune(len(good), qs, ep, c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), 0, None,
+                                       0, None, reps, o, ctypes.byref(st)) == mpdp.MPDP_EINVAL
+
+    h = ctypes.c_void_p(1)
+    assert lib.mpdp_batch_graph_create(len(good), qs, 0, None, 0, None) == mpdp.MPDP_EINVAL
+    assert lib.mpdp_batch_graph_create(len(good), qs, 0, None, 0, ctypes.byref(h)) == mpdp.MPDP_EINVAL
+    assert h.value is None  # NULL on error
+    assert lib.mpdp_batch_graph_create(len(good), qs, 7, None, 0, ctypes.byref(h)) == mpdp.MPDP_EINVAL
+    big, _, _, _ = mpdp._batch_marshal([W.chain(21, 2)])
+    assert lib.mpdp_batch_graph_create(1, big, 0, None, 0, ctypes.byref(h)) == mpdp.MPDP_ETOOLARGE
+    short = (mpdp.mpdp_batch_query * 1)(mpdp.mpdp_batch_query(5, 3, 0, 0))  # m < n - 1
+    assert lib.mpdp_batch_graph_create(1, short, 0, None, 0, ctypes.byref(h)) == mpdp.MPDP_EINVAL
+    assert lib.mpdp_batch_graph_run(None, qs, ep, c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), None, None,
+                                    plans, costs.ctypes.data_as(f64p), None, None) == mpdp.MPDP_EINVAL
+    lib.mpdp_batch_graph_destroy(None)
