@@ -16,7 +16,9 @@ Besides the headline (timed region: the star-25 steps only), the same JSON
 line carries two untimed reports:
 batch      4096 mixed queries of 8-20 relations in one persistent launch:
            kernel time, per-query latency p50/p99 (device clock from the
-           launch start), queries/s
+           launch start), queries/s; then the per-query schedules chosen by
+           the library's autotuner and the batch replayed as one captured HIP
+           graph with them (graph_tuned)
 large      100-1000 relations (snowflake, depth 4, random cross edges):
            GOO, IDP2 (k 15, 25), UnionDP (k 15) and the learned UnionDP
            (k 15, scorer trained on the GPU first): plan cost normalized to
@@ -286,6 +288,41 @@ def bench_batch(mpdp, workloads, np, count=4096, runs=3):
             "latency_us_p99": float(lat[int(0.99 * (len(lat) - 1))]),
             "latency_us_max": float(lat[-1]),
             "ccp_pairs_per_s": r.stats["ccp_pairs"] / (r.stats["ms_kernel"] / 1e3),
+        }
+        # per-query schedules from the autotuner (untimed), then the batch as
+        # one captured HIP graph replayed with those schedules
+        t = time.perf_counter()
+        sched, tst = mpdp.mpdp_batch_autotune(qs, cm, ws, reps=2)
+        tune_s = time.perf_counter() - t
+        g = mpdp.BatchGraph(qs, cm, ws)
+        try:
+            g.run(qs, schedules=sched)  # warm-up
+            gbest = None
+            for _ in range(runs):
+                t = time.perf_counter()
+                gr = g.run(qs, schedules=sched)
+                gwall = (time.perf_counter() - t) * 1e3
+                if gbest is None or gwall < gbest[1]:
+                    gbest = (gr, gwall)
+        finally:
+            g.close()
+        gr, gwall = gbest
+        assert gr.costs == r.costs  # schedules and replay leave every result unchanged
+        glat = np.sort(gr.latency_us)
+        picked = {}
+        for tc, hc in sched:
+            picked[f"{tc}/{hc}"] = picked.get(f"{tc}/{hc}", 0) + 1
+        out[name]["graph_tuned"] = {
+            "call_ms": gwall,
+            "span_ms": float(glat[-1]) / 1e3,
+            "queries_per_s": count / (float(glat[-1]) / 1e6),  # device span, as kernel_ms above
+            "queries_per_s_call": count / (gwall / 1e3),        # host call, packing and unpacking included
+            "latency_us_p50": float(glat[len(glat) // 2]),
+            "latency_us_p99": float(glat[int(0.99 * (len(glat) - 1))]),
+            "latency_us_max": float(glat[-1]),
+            "tuning_s": tune_s, "tune_classes": tst["classes"], "tune_launches": tst["launches"],
+            "est_default_ms": tst["est_default_ms"], "est_tuned_ms": tst["est_tuned_ms"],
+            "schedules_tree_chunk_over_heavy_chunks": picked,
         }
     del ws
     torch.cuda.empty_cache()
