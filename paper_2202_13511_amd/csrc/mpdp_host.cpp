@@ -58,7 +58,19 @@ struct Query {
     int cost_model;
     bool is_tree;
     DevGraph g;
+    double sel_full[32 * 32];  // host only: sel[u * 32 + v], symmetric, 0 without an edge
 };
+
+// C(a, b) for a, b <= 32 at [a * 33 + b], computed once.
+const uint32_t *binom_table() {
+    static const std::vector<uint32_t> t = [] {
+        std::vector<uint32_t> v(33 * 33);
+        for (uint32_t a = 0; a <= 32; ++a)
+            for (uint32_t b = 0; b <= 32; ++b) v[a * 33 + b] = (uint32_t)binom64(a, b);
+        return v;
+    }();
+    return t.data();
+}
 
 // Validation runs entirely on the host, before any HIP call.  base_costs
 // (may be null) gives each relation the cost of an already planned
@@ -96,8 +108,8 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
         if (!std::isfinite(sel[i]) || !(sel[i] > 0.0) || !(sel[i] <= 1.0)) return MPDP_EINVAL;
         L.adj[u] |= 1u << v;
         L.adj[v] |= 1u << u;
-        g.sel_full[u * 32 + v] = sel[i];
-        g.sel_full[v * 32 + u] = sel[i];
+        q.sel_full[u * 32 + v] = sel[i];
+        q.sel_full[v * 32 + u] = sel[i];
     }
     // connectivity of the whole join graph (no cross products, Section 2.1.1)
     const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
@@ -140,31 +152,26 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
         const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
         L.lo1[v] = lower & (0u - lower);
         L.lorest[v] = lower & ~L.lo1[v];
-        L.sel1[v] = lower ? g.sel_full[__builtin_ctz(lower) * 32 + v] : 1.0;
+        L.sel1[v] = lower ? q.sel_full[__builtin_ctz(lower) * 32 + v] : 1.0;
         for (uint32_t t = lower; t; t &= t - 1)
-            L.sel[at++] = g.sel_full[__builtin_ctz(t) * 32 + v];
+            L.sel[at++] = q.sel_full[__builtin_ctz(t) * 32 + v];
     }
     for (uint32_t v = n; v < 32; ++v) L.sel1[v] = 1.0;
-    for (int b = 0; b < 4; ++b)
-        for (uint32_t x = 0; x < 256; ++x) {
-            uint32_t u = 0;
-            for (int j = 0; j < 8; ++j)
-                if ((x >> j) & 1u) {
-                    const uint32_t v = 8u * b + j;
-                    if (v < n) u |= L.adj[v];
-                }
-            L.nb[b][x] = u;
-        }
+    // byte tables: entry x is entry x without its lowest bit, plus that
+    // relation's row (relations beyond n have empty rows)
+    uint32_t kids[32] = {0};  // tree joins: children of each relation
     if (q.is_tree)
-        for (int b = 0; b < 4; ++b)
-            for (uint32_t x = 0; x < 256; ++x) {
-                uint32_t c = 0;
-                for (uint32_t v = 1; v < n; ++v)  // v's parent is the member of pbit[v]
-                    if (L.pbit[v] & (x << (8u * b))) c |= 1u << v;
-                L.ch[b][x] = c;
-            }
-    for (uint32_t a = 0; a <= 32; ++a)
-        for (uint32_t b = 0; b <= 32; ++b) L.binom[a * 33 + b] = (uint32_t)binom64(a, b);
+        for (uint32_t v = 1; v < n; ++v) kids[__builtin_ctz(L.pbit[v])] |= 1u << v;
+    for (int b = 0; b < 4; ++b) {
+        L.nb[b][0] = 0;
+        L.ch[b][0] = 0;
+        for (uint32_t x = 1; x < 256; ++x) {
+            const uint32_t v = 8u * b + (uint32_t)__builtin_ctz(x);
+            L.nb[b][x] = L.nb[b][x & (x - 1)] | (v < n ? L.adj[v] : 0u);
+            L.ch[b][x] = L.ch[b][x & (x - 1)] | kids[v];
+        }
+    }
+    std::memcpy(L.binom, binom_table(), sizeof(L.binom));
     uint64_t off = 0;
     for (uint32_t k = 0; k < 34; ++k) {
         L.loff[k] = off;
@@ -247,17 +254,15 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 6], s));
     }
     HIPCHK(mpdp::launch_extract(dg, n, memo, dplan, droot, cnt, s));
-    std::vector<mpdp_plan_node> plan(2 * n - 1);
-    Counters hc{};
-    double root = 0.0;
-    HIPCHK(hipMemcpyAsync(plan.data(), dplan, sizeof(mpdp_plan_node) * (2 * n - 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&root, droot, sizeof(double), hipMemcpyDeviceToHost, s));
+    // counters, plan and root cost are adjacent in the workspace: one copy back
+    std::vector<char> down(L.root + sizeof(double) - L.counters);
+    HIPCHK(hipMemcpyAsync(down.data(), cnt, down.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    Counters hc;
+    std::memcpy(&hc, down.data(), sizeof(Counters));
     if (hc.extract_error) return MPDP_EDEVICE;
-
-    std::memcpy(plan_out, plan.data(), sizeof(mpdp_plan_node) * (2 * n - 1));
-    *cost_out = root;
+    std::memcpy(plan_out, down.data() + (L.plan - L.counters), sizeof(mpdp_plan_node) * (2 * n - 1));
+    std::memcpy(cost_out, down.data() + (L.root - L.counters), sizeof(double));
     if (stats_out) {
         mpdp_stats st{};
         st.candidates = candidates;
@@ -420,9 +425,7 @@ void fill_batch_upload(char *up, const BatchLayout &B, uint32_t nq, const mpdp_b
                        const mpdp_edge *edges, const double *cardinalities, const double *selectivities,
                        const double *base_costs, mpdp_cost_model cost_model, const mpdp_batch_schedule *sched) {
     std::memset(up, 0, B.plans);
-    uint32_t *binom = reinterpret_cast<uint32_t *>(up + B.binom);
-    for (uint32_t a = 0; a <= 32; ++a)
-        for (uint32_t b = 0; b <= 32; ++b) binom[a * 33 + b] = (uint32_t)binom64(a, b);
+    std::memcpy(up + B.binom, binom_table(), 33 * 33 * sizeof(uint32_t));
     auto *bc = reinterpret_cast<mpdp::BatchCounters *>(up + B.counters);
     bc->next = 0;
     bc->pad = 0;

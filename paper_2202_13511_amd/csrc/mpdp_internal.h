@@ -40,7 +40,6 @@ struct DevGraph {
     LdsImage lds;
     uint32_t n, m, is_tree, cost_model;
     uint32_t ablate, pad[3];             // kAblateDpsub: every connected set is one block (DPSUB's enumeration)
-    double sel_full[kMaxRel * kMaxRel];  // sel[u * 32 + v], symmetric, 0 without an edge
 };
 
 // Memo, level-compact: the entry of a relation set S sits at
