@@ -196,6 +196,21 @@ mpdp_status leaf_only(const Query &q, mpdp_plan_node *plan, double *cost_out) {
         if ((expr) != hipSuccess) return MPDP_EDEVICE; \
     } while (0)
 
+// Pinned host staging of the calling thread, at least `bytes` (kept for the
+// process's lifetime; nullptr if pinned memory cannot be had, and the caller
+// then copies from pageable memory).
+char *pinned_staging(size_t bytes) {
+    thread_local char *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (cap >= bytes) return buf;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (buf) (void)hipHostFree(buf);
+    buf = static_cast<char *>(p);
+    cap = bytes;
+    return buf;
+}
+
 struct EventPool {
     std::vector<hipEvent_t> ev;
     ~EventPool() {
@@ -234,7 +249,17 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
 
     DevGraph *hg = const_cast<DevGraph *>(&q.g);
     hg->ablate = (flags & MPDP_FLAG_ABLATE_DPSUB) ? mpdp::kAblateDpsub : 0u;
-    HIPCHK(hipMemcpyAsync(dg, &q.g, sizeof(DevGraph), hipMemcpyHostToDevice, s));
+    // upload and readback go through this thread's pinned staging buffer
+    // (plain DMA, no runtime-side staging copy); the call waits for its
+    // stream before returning, so the buffer is free again by the next call
+    const size_t down_bytes = L.root + sizeof(double) - L.counters;
+    char *pin = pinned_staging(sizeof(DevGraph) > down_bytes ? sizeof(DevGraph) : down_bytes);
+    if (pin) {
+        std::memcpy(pin, &q.g, sizeof(DevGraph));
+        HIPCHK(hipMemcpyAsync(dg, pin, sizeof(DevGraph), hipMemcpyHostToDevice, s));
+    } else {
+        HIPCHK(hipMemcpyAsync(dg, &q.g, sizeof(DevGraph), hipMemcpyHostToDevice, s));
+    }
     HIPCHK(mpdp::launch_init(dg, n, memo, cnt, s));
     const bool general = force_general || !q.is_tree;
     uint64_t candidates = 0;
@@ -255,14 +280,15 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     }
     HIPCHK(mpdp::launch_extract(dg, n, memo, dplan, droot, cnt, s));
     // counters, plan and root cost are adjacent in the workspace: one copy back
-    std::vector<char> down(L.root + sizeof(double) - L.counters);
-    HIPCHK(hipMemcpyAsync(down.data(), cnt, down.size(), hipMemcpyDeviceToHost, s));
+    std::vector<char> down_pageable(pin ? 0 : down_bytes);
+    char *down = pin ? pin : down_pageable.data();
+    HIPCHK(hipMemcpyAsync(down, cnt, down_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     Counters hc;
-    std::memcpy(&hc, down.data(), sizeof(Counters));
+    std::memcpy(&hc, down, sizeof(Counters));
     if (hc.extract_error) return MPDP_EDEVICE;
-    std::memcpy(plan_out, down.data() + (L.plan - L.counters), sizeof(mpdp_plan_node) * (2 * n - 1));
-    std::memcpy(cost_out, down.data() + (L.root - L.counters), sizeof(double));
+    std::memcpy(plan_out, down + (L.plan - L.counters), sizeof(mpdp_plan_node) * (2 * n - 1));
+    std::memcpy(cost_out, down + (L.root - L.counters), sizeof(double));
     if (stats_out) {
         mpdp_stats st{};
         st.candidates = candidates;
