@@ -31,9 +31,10 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
     if (t < kMaxRel) {
         L.adj[t] = 0;
         L.pbit[t] = 0;
-        L.lo1[t] = 0;
-        L.lorest[t] = 0;
-        L.sel1[t] = 1.0;
+        L.lo[t][0] = 0;
+        L.lo[t][1] = 0;
+        L.csel[t][0] = t < n ? C[t] : 1.0;
+        L.csel[t][1] = 1.0;
         L.desc[t] = 1u << t;
         L.card[t] = t < n ? C[t] : 1.0;
         if (t >= n) L.bcost[t] = 0.0;
@@ -57,9 +58,9 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
             const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
             if (hi == t) L.sel[start + (uint32_t)popc32(lower & ((1u << lo) - 1u))] = SL[e];
         }
-        L.lo1[t] = lower & (0u - lower);
-        L.lorest[t] = lower & ~(lower & (0u - lower));
-        L.sel1[t] = lower ? L.sel[start] : 1.0;  // written by this thread above
+        L.lo[t][0] = lower & (0u - lower);
+        L.lo[t][1] = lower & ~(lower & (0u - lower));
+        L.csel[t][1] = lower ? L.sel[start] : 1.0;  // written by this thread above
     }
     for (uint32_t i = t; i < 4 * 256; i += blockDim.x) {
         const uint32_t byte = i >> 8, x = i & 255u;
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                                                        BatchCounters *bc) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ uint32_t rings[kBW][kRing];
+    __shared__ uint32_t ring_ranks[kBW][kRing];
     __shared__ WaveScratch WS[kBW];
     __shared__ SetBlocks hsb;
     __shared__ Key hkeys[kBW];
@@ -167,15 +169,15 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 switch (Q.sched & kSchedChunkMask) {  // consecutive ranks per lane
                     case 0:
                         found = level_tree_wave<CM, 1>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 63) / 64,
-                                                       rings[wave], lane);
+                                                       rings[wave], ring_ranks[wave], lane);
                         break;
                     case 1:
                         found = level_tree_wave<CM, 2>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 127) / 128,
-                                                       rings[wave], lane);
+                                                       rings[wave], ring_ranks[wave], lane);
                         break;
                     default:
                         found = level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 255) / 256,
-                                                       rings[wave], lane);
+                                                       rings[wave], ring_ranks[wave], lane);
                         break;
                 }
                 if (lane == 0 && found) atomicAdd(&s_level, found);

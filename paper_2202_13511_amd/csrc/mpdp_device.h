@@ -81,6 +81,16 @@ __device__ __forceinline__ void stage_graph(const DevGraph *g, LdsGraph &L) {
     __syncthreads();
 }
 
+// Copy the first `bytes` (a multiple of 16) of the host-built LDS image: the
+// tree kernel keeps only that prefix (kTreeLdsBytes) in LDS.
+__device__ __forceinline__ void stage_graph_prefix(const DevGraph *g, unsigned char *dst_raw, size_t bytes) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(&g->lds);
+    uint4 *dst = reinterpret_cast<uint4 *>(dst_raw);
+    for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+static_assert(kTreeLdsBytes % 16 == 0, "the tree prefix is copied in 16-byte units");
+
 // Memo index of T: level offset plus colex rank.
 __device__ __forceinline__ uint64_t memo_index(const LdsGraph &L, uint32_t T) {
     uint32_t r = 0;
@@ -223,28 +233,30 @@ __device__ __forceinline__ void offer_if(bool on, Key &best, double cost, uint32
 }
 
 template <int CM>
-__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t k,
-                                              uint64_t off_k, const double *__restrict__ cost_km1,
+__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t rank,
+                                              uint32_t k, uint64_t off_k, const double *__restrict__ cost_km1,
                                               const double *__restrict__ card_km1) {
-    constexpr int kPairBatch = (CM == MPDP_COST_COUT) ? 4 : 4;
-    // one pass over S: its colex rank, the sum of C(s_i, i), and card(S) in
-    // card_of's order (members ascending, each card then the selectivities of
-    // its edges to smaller members, ascending).  The edge to v's lowest
-    // smaller neighbour comes from sel1 (times an exact 1.0 when that
-    // neighbour is outside S); v's other smaller neighbours in S, which a
-    // tree seldom has, go through the sel row.
-    uint32_t rank = 0, bsum = 0;
+    constexpr int kPairBatch = 4;
+    // One pass over S: bsum = sum of C(s_i, i), and card(S) in card_of's
+    // order (members ascending, each card then the selectivities of its
+    // edges to smaller members, ascending).  The edge to v's lowest smaller
+    // neighbour comes from the (card, sel) pair of v (times an exact 1.0 when
+    // that neighbour is outside S); v's other smaller neighbours in S, which
+    // a tree seldom has, go through the sel row.  S's own colex rank comes
+    // with it from the filter.
     double c = 1.0;
+    uint32_t bsum = 0;
     {
         uint32_t T = S;
         for (uint32_t i = 0; i < k; ++i) {
             const int v = ctz32(T);
             T &= T - 1;
-            rank += L.binom[v * 33 + i + 1];
             bsum += L.binom[v * 33 + i];
-            c = c * L.card[v];
-            c = c * ((S & L.lo1[v]) ? L.sel1[v] : 1.0);
-            const uint32_t rest = L.lorest[v] & S;
+            const double2 cs = *reinterpret_cast<const double2 *>(L.csel[v]);
+            const uint2 lo = *reinterpret_cast<const uint2 *>(L.lo[v]);
+            c = c * cs.x;
+            c = c * ((S & lo.x) ? cs.y : 1.0);
+            const uint32_t rest = lo.y & S;
             if (rest) {
                 const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
                 for (uint32_t U = rest; U; U &= U - 1)
@@ -265,18 +277,19 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
         uint32_t Av[kPairBatch], rk[kPairBatch], ba[kPairBatch], bb[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
+            const uint32_t i = i0 + (uint32_t)u;
+            const bool live = i < k;
             const int m = ctz32(T | 0x80000000u);
             T &= T - 1;
-            const uint32_t i = i0 + (uint32_t)u;
             bb[u] = L.binom[m * 33 + i];
             ba[u] = L.binom[m * 33 + i + 1];
             const uint32_t par = L.pbit[m], below = L.desc[m];
-            Av[u] = ((i < k) & ((S & par) != 0)) ? (below & S) : 0u;
+            Av[u] = (live & ((S & par) != 0)) ? (below & S) : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
+            // a slot past the last member gathers entry 0
             pb += bb[u];
-            // colex rank of S - {m}; a slot past the last member gathers entry 0
             rk[u] = (i0 + (uint32_t)u < k) ? pa + (bsum - pb) : 0u;
             pa += ba[u];
         }
@@ -680,7 +693,8 @@ __device__ __forceinline__ uint64_t memo_index_t(const uint32_t *binom, const ui
 // connected sets it found (uniform across the wave).
 template <int CM, int kTreeChunk, bool kCompact = true>
 __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
-                                    uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *ring, uint32_t lane) {
+                                    uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *ring,
+                                    uint32_t *ring_rank, uint32_t lane) {
     static_assert(kRing >= 63 + 64 * kTreeChunk, "ring too small");
     const unsigned long long below_me = (1ull << lane) - 1ull;
     const uint64_t per_wave = 64ull * kTreeChunk;
@@ -712,7 +726,8 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         if (!kCompact) {  // ablation: each lane evaluates the sets it kept, lanes diverge
 #pragma unroll
             for (int j = 0; j < kTreeChunk; ++j)
-                if (keep & (1u << j)) eval_tree_set<CM>(L, M, sets[j], k, off_k, cost_km1, card_km1);
+                if (keep & (1u << j))
+                    eval_tree_set<CM>(L, M, sets[j], (uint32_t)(r0 + j), k, off_k, cost_km1, card_km1);
             tail += total;
             head = tail;
             continue;
@@ -720,19 +735,23 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         uint32_t pos = tail + before;
 #pragma unroll
         for (int j = 0; j < kTreeChunk; ++j)
-            if (keep & (1u << j)) ring[(pos++) % kRing] = sets[j];
+            if (keep & (1u << j)) {
+                ring[pos % kRing] = sets[j];
+                ring_rank[pos % kRing] = (uint32_t)(r0 + j);
+                ++pos;
+            }
         tail += total;
         wave_sync_lds();
         while (tail - head >= 64) {
-            const uint32_t s = ring[(head + lane) % kRing];
-            eval_tree_set<CM>(L, M, s, k, off_k, cost_km1, card_km1);
+            const uint32_t s = ring[(head + lane) % kRing], r = ring_rank[(head + lane) % kRing];
+            eval_tree_set<CM>(L, M, s, r, k, off_k, cost_km1, card_km1);
             head += 64;
         }
         wave_sync_lds();
     }
     if (tail != head && lane < tail - head) {
-        const uint32_t s = ring[(head + lane) % kRing];
-        eval_tree_set<CM>(L, M, s, k, off_k, cost_km1, card_km1);
+        const uint32_t s = ring[(head + lane) % kRing], r = ring_rank[(head + lane) % kRing];
+        eval_tree_set<CM>(L, M, s, r, k, off_k, cost_km1, card_km1);
     }
     wave_sync_lds();
     return tail;

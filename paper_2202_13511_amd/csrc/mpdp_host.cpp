@@ -150,13 +150,14 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
     for (uint32_t v = 0; v < n; ++v) {
         L.selrow[v] = at;
         const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
-        L.lo1[v] = lower & (0u - lower);
-        L.lorest[v] = lower & ~L.lo1[v];
-        L.sel1[v] = lower ? q.sel_full[__builtin_ctz(lower) * 32 + v] : 1.0;
+        L.lo[v][0] = lower & (0u - lower);
+        L.lo[v][1] = lower & ~L.lo[v][0];
+        L.csel[v][0] = L.card[v];
+        L.csel[v][1] = lower ? q.sel_full[__builtin_ctz(lower) * 32 + v] : 1.0;
         for (uint32_t t = lower; t; t &= t - 1)
             L.sel[at++] = q.sel_full[__builtin_ctz(t) * 32 + v];
     }
-    for (uint32_t v = n; v < 32; ++v) L.sel1[v] = 1.0;
+    for (uint32_t v = n; v < 32; ++v) L.csel[v][0] = L.csel[v][1] = 1.0;
     // byte tables: entry x is entry x without its lowest bit, plus that
     // relation's row (relations beyond n have empty rows)
     uint32_t kids[32] = {0};  // tree joins: children of each relation

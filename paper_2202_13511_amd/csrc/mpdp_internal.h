@@ -15,23 +15,30 @@ constexpr int kMaxRel = 32;
 
 // Per-workgroup copy of the query information, laid out on the host exactly
 // as the kernels keep it in LDS so that staging is a plain 16-byte copy.
+// The tree kernel reads only a prefix (kTreeLdsBytes: everything before the
+// selectivity rows, plus the rows of a tree's n - 1 <= 31 edges), so the
+// selectivity rows and the neighbour tables, which only the block-based
+// kernels read in full, come last.
 struct LdsImage {
     uint64_t loff[34];                        // memo offset of level k: sum of C(n, j), j < k
     double card[kMaxRel];
     double bcost[kMaxRel];                    // cost of scanning relation v under the model
-    double sel[kMaxRel * (kMaxRel - 1) / 2];  // per v: sel(u, v) of edges u < v, u ascending
-    double sel1[kMaxRel];                     // sel(lowest u < v adjacent to v, v); 1.0 without one
-    uint32_t nb[4][256];                      // neighbours of a set, one table per bitmap byte
+    double csel[kMaxRel][2];                  // per v: card[v], then sel(lowest u < v adjacent to v, v) (1.0 without one)
     uint32_t ch[4][256];                      // tree joins rooted at 0: children of a set, per byte
+    uint32_t lo[kMaxRel][2];                  // per v: bit of its lowest neighbour u < v (0 without one), its other neighbours u < v
     uint32_t adj[kMaxRel];                    // bit u of adj[v]: edge (u, v)
     uint32_t pbit[kMaxRel];                   // tree joins rooted at 0: bit of the parent, 0 at the root
     uint32_t desc[kMaxRel];                   // tree joins: relations of the subtree rooted at v
     uint32_t selrow[kMaxRel];                 // first sel entry of relation v
-    uint32_t lo1[kMaxRel];                    // bit of the lowest neighbour u < v of v, 0 without one
-    uint32_t lorest[kMaxRel];                 // the other neighbours u < v of v
     uint32_t binom[33 * 33];                  // C(a, b) at [a * 33 + b]
     uint32_t pad[3];
+    double sel[kMaxRel * (kMaxRel - 1) / 2];  // per v: sel(u, v) of edges u < v, u ascending
+    uint32_t nb[4][256];                      // neighbours of a set, one table per bitmap byte
 };
+static_assert(offsetof(LdsImage, csel) % 16 == 0, "(card, sel) pairs are read as 16-byte units");
+static_assert(offsetof(LdsImage, lo) % 8 == 0, "lowest-neighbour pairs are read as 8-byte units");
+static_assert(offsetof(LdsImage, sel) % 16 == 0, "the tree prefix ends on a 16-byte boundary");
+constexpr size_t kTreeLdsBytes = offsetof(LdsImage, sel) + 8 * 32;  // the prefix plus 32 selectivities
 static_assert(sizeof(LdsImage) % 16 == 0, "LdsImage is copied in 16-byte units");
 
 // Query information as the kernels read it.  Built on the host, uploaded

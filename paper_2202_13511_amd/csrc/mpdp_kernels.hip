@@ -46,9 +46,13 @@ __global__ void k_init(const DevGraph *g, uint32_t n, MemoPtrs M, Counters *cnt)
 template <int CM, int kTreeChunk, bool kCompact>
 __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32_t k, uint64_t ncand,
                                                        Counters *cnt, MemoPtrs M) {
-    __shared__ __align__(16) LdsGraph L;
+    // the LDS image up to the first 32 selectivities: a tree join reads no
+    // more (n - 1 <= 31 edges, and no neighbour tables)
+    __shared__ __align__(16) unsigned char lds_tree[kTreeLdsBytes];
     __shared__ uint32_t ring_all[kWaves][kRing];
-    stage_graph(g, L);
+    __shared__ uint32_t ring_rank_all[kWaves][kRing];
+    stage_graph_prefix(g, lds_tree, kTreeLdsBytes);
+    const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t per_wave = 64ull * kTreeChunk;
     const uint64_t nw = (ncand + per_wave - 1) / per_wave;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
         we = nw * (x + 1) / 8;
     }
     const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact>(
-        L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], lane);
+        L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_rank_all[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
 
