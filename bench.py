@@ -365,7 +365,10 @@ def bench_large(mpdp, workloads, np):
     from paper_2202_13511_amd import scorer
     M = mpdp
     methods = [("goo", M.MPDP_LARGE_GOO, 2), ("idp2_15", M.MPDP_LARGE_IDP2, 15), ("idp2_25", M.MPDP_LARGE_IDP2, 25),
-               ("uniondp_15", M.MPDP_LARGE_UNIONDP, 15), ("learned_uniondp_15", M.MPDP_LARGE_UNIONDP_LEARNED, 15)]
+               ("uniondp_15", M.MPDP_LARGE_UNIONDP, 15), ("uniondp_20", M.MPDP_LARGE_UNIONDP, 20),
+               ("uniondp_25", M.MPDP_LARGE_UNIONDP, 25), ("learned_uniondp_15", M.MPDP_LARGE_UNIONDP_LEARNED, 15),
+               ("learned_uniondp_25", M.MPDP_LARGE_UNIONDP_LEARNED, 25)]
+    plain_uniondp = ("uniondp_15", "uniondp_20", "uniondp_25")
     res = {"workload": "large_snowflake(n, seed): depth <= 4, round(n/20) cross edges; n in {100, 300, 1000}, "
                        "seeds 0..2; costs normalized to the best plan found per query",
            "train": {}, "cost_models": {}}
@@ -376,6 +379,8 @@ def bench_large(mpdp, workloads, np):
                                "final_loss": log.loss[-1]}
         per_n = {}
         ratios_lp = []
+        ratios_eq = []  # learned (k 15 or 25) vs the best plain UnionDP run that took no longer
+        ratios_lp25 = []
         for n in (100, 300, 1000):
             rows = {name: [] for name, _, _ in methods}
             times = {name: [] for name, _, _ in methods}
@@ -391,6 +396,11 @@ def bench_large(mpdp, workloads, np):
                 for name in costs:
                     rows[name].append(costs[name] / best)
                 ratios_lp.append(costs["learned_uniondp_15"] / costs["uniondp_15"])
+                ratios_lp25.append(costs["learned_uniondp_25"] / costs["uniondp_25"])
+                for ln, pk in (("learned_uniondp_15", "uniondp_15"), ("learned_uniondp_25", "uniondp_25")):
+                    t_l = times[ln][-1]
+                    eq = [costs[nm] for nm in plain_uniondp if times[nm][-1] <= t_l] or [costs[pk]]
+                    ratios_eq.append(costs[ln] / min(eq))
             per_n[str(n)] = {name: {"cost_ratio_mean": float(np.mean(rows[name])),
                                     "ms_mean": float(np.mean(times[name]))} for name in rows}
         held = scorer.training_queries(40, 99)
@@ -398,6 +408,8 @@ def bench_large(mpdp, workloads, np):
         res["cost_models"][cname] = {
             "by_n": per_n,
             "learned_vs_plain_uniondp_geomean": float(np.exp(np.mean(np.log(ratios_lp)))),
+            "learned_vs_plain_uniondp_k25_geomean": float(np.exp(np.mean(np.log(ratios_lp25)))),
+            "learned_vs_plain_uniondp_equal_time_geomean": float(np.exp(np.mean(np.log(ratios_eq)))),
             "small_vs_exact_geomean": {"uniondp_15": float(np.exp(np.mean(np.log(plain)))),
                                        "learned_uniondp_15": float(np.exp(np.mean(np.log(learned))))},
         }
