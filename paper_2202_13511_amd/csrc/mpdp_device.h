@@ -99,15 +99,21 @@ __device__ __forceinline__ uint64_t memo_index(const LdsGraph &L, uint32_t T) {
     return L.loff[i - 1] + r;
 }
 
-// Colex unrank of rank r among the k-subsets of n relations.
+// Colex unrank of rank r among the k-subsets of n relations: relations from
+// n - 1 down, relation c is the next member (i still to place) exactly when
+// C(c, i) <= r, the largest such c being the first met.  One uniform,
+// branch-free step per relation; C(c, i) = 0 for c < i takes the last
+// members once r has reached 0.
 __device__ __forceinline__ uint32_t colex_unrank(const uint32_t *binom, int n, int k, uint32_t r) {
     uint32_t S = 0;
-    int c = n - 1;
-    for (int i = k; i >= 1; --i) {
-        while (binom[c * 33 + i] > r) --c;
-        r -= binom[c * 33 + i];
-        S |= 1u << c;
-        --c;
+    int i = k;
+#pragma unroll 4
+    for (int c = n - 1; c >= 0; --c) {
+        const uint32_t t = binom[c * 33 + i];
+        const bool take = (i > 0) & (t <= r);
+        r -= take ? t : 0u;
+        S |= take ? (1u << c) : 0u;
+        i -= take ? 1 : 0;
     }
     return S;
 }
