@@ -25,6 +25,9 @@ large      100-1000 relations (snowflake, depth 4, random cross edges):
            the best plan found per query, and optimization time; the learned
            vs plain UnionDP cost ratio; and on held-out 20-26 relation
            queries both UnionDPs' ratio to the exact optimum
+configs    the paper-shaped single queries: star 12, snowflake 25 (both
+           models), cycle of 20-30 relations plus 5-15 chords, clique 18:
+           optimize time median / p99 over the seeds, ccp pairs per second
 ablations  the same optimizer with DPSUB's vertex-based candidates on the GPU,
            and the tree kernel without its LDS compaction (results unchanged)
 cpu_allcores  the library's multi-threaded CPU MPDP on the star (16 threads
@@ -88,6 +91,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -226,6 +230,8 @@ def main() -> int:
     if not args.no_batch:
         out["batch"] = bench_batch(mpdp, workloads, np)
 
+    if not args.no_configs:
+        out["configs"] = bench_configs(mpdp, workloads, np, dev)
     if not args.no_large:
         out["large"] = bench_large(mpdp, workloads, np)
 
@@ -328,6 +334,44 @@ def bench_batch(mpdp, workloads, np, count=4096, runs=3):
     torch.cuda.empty_cache()
     return {"workload": f"{count} queries, n ~ U{{8..20}}, chain/star/cycle/snowflake/random mix, seed 0",
             "workgroups": 512, "runs": runs, **out}
+
+
+def bench_configs(mpdp, workloads, np, dev):
+    """The paper-shaped single-query workloads (untimed by the headline):
+    end-to-end optimize time per query (best of `reps` after a warm-up),
+    median and p99 over the seeds, and ccp pairs per second over all of
+    them.  C3a runs each seed once: its larger queries take up to a second."""
+    import torch
+    specs = [("C1 star12", lambda s: workloads.star(12, s), 64, (mpdp.MPDP_COST_COUT,), 3),
+             ("C2 snowflake25", lambda s: workloads.snowflake(25, s), 64,
+              (mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE), 2),
+             ("C3a cycle20-30+5-15 chords", lambda s: workloads.cycle_chords(s), 32, (mpdp.MPDP_COST_COUT,), 0),
+             ("C3b clique18", lambda s: workloads.clique(18, s), 32,
+              (mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE), 1)]
+    out = {}
+    for name, gen, seeds, cms, reps in specs:
+        qs = [gen(s) for s in range(seeds)]
+        for cm in cms:
+            ws = mpdp.workspace(max(q.n for q in qs), cm, dev)
+            mpdp.mpdp_optimize_ws(qs[0], cm, ws)  # warm-up
+            ms, ccp = [], 0
+            for q in qs:
+                best = None
+                for _ in range(max(reps, 1)):
+                    t = time.perf_counter()
+                    r = mpdp.mpdp_optimize_ws(q, cm, ws)
+                    dt = (time.perf_counter() - t) * 1e3
+                    best = dt if best is None else min(best, dt)
+                ms.append(best)
+                ccp += r.stats["ccp_pairs"]
+            del ws
+            torch.cuda.empty_cache()
+            ms_s = sorted(ms)
+            out[f"{name} {'C_out' if cm == mpdp.MPDP_COST_COUT else 'PG-like'}"] = {
+                "queries": seeds, "optimize_ms_median": float(ms_s[len(ms_s) // 2]),
+                "optimize_ms_p99": float(ms_s[min(len(ms_s) - 1, int(round(0.99 * (len(ms_s) - 1))))]),
+                "optimize_ms_max": float(ms_s[-1]), "ccp_pairs_per_s": ccp / (sum(ms) / 1e3)}
+    return out
 
 
 def bench_ablations(mpdp, workloads, dev, reps=5):
