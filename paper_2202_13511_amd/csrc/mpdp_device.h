@@ -603,6 +603,12 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
             const uint32_t lb = lo | sub, rb = b ^ lb;
             sub = (sub - rest) & rest;
             if (!full) {
+                // a connected side of two or more relations has no member
+                // without a neighbour on its side: four table lookups
+                // reject most disconnected candidates of a sparse block
+                // before the breadth-first check
+                if ((lb & (lb - 1)) && (lb & ~nbrs(L.nb, lb))) continue;
+                if ((rb & (rb - 1)) && (rb & ~nbrs(L.nb, rb))) continue;
                 if (grow(L.nb, lo, lb) != lb) continue;
                 if (grow(L.nb, lowbit(rb), rb) != rb) continue;
             }
