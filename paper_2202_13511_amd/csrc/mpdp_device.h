@@ -18,6 +18,13 @@ constexpr int kFilterChunk = 16;    // consecutive ranks per lane in k_filter (<
 constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tree (1, 2 or 4)
 constexpr int kRing = 384;          // per-wave ring of connected sets (>= 63 + 64 * kTreeChunkMax)
 constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
+// Tree levels with at least kTreeSplitMinK members per set (two or more
+// batches of gathers for one lane) and at most kTreeSplitMaxCand candidates
+// are too small to hide a lane's serial gathers: kTreeSplitLanes lanes take
+// each candidate there.
+constexpr int kTreeSplitLanes = 8;
+constexpr uint32_t kTreeSplitMinK = 8;
+constexpr uint64_t kTreeSplitMaxCand = 4096;
 constexpr uint32_t kHeavyChunks = 256;   // above this many 16-candidate chunks a set is heavy
 constexpr int kHeavyBlock = 1024;        // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
@@ -238,39 +245,45 @@ __device__ __forceinline__ void offer_if(bool on, Key &best, double cost, uint32
     if (CM != MPDP_COST_COUT) best.op = take ? op : best.op;
 }
 
+// One pass over the k members of a tree-inducing S: bsum = sum of C(s_i, i),
+// and card(S) in card_of's order (members ascending, each card then the
+// selectivities of its edges to smaller members, ascending).  The edge to
+// v's lowest smaller neighbour comes from the (card, sel) pair of v (times
+// an exact 1.0 when that neighbour is outside S); v's other smaller
+// neighbours in S, which a tree seldom has, go through the sel row.
+__device__ __forceinline__ void tree_bsum_card(const LdsGraph &L, uint32_t S, uint32_t k, uint32_t &bsum,
+                                               double &cardS) {
+    double c = 1.0;
+    uint32_t b = 0;
+    uint32_t T = S;
+    for (uint32_t i = 0; i < k; ++i) {
+        const int v = ctz32(T);
+        T &= T - 1;
+        b += L.binom[v * 33 + i];
+        const double2 cs = *reinterpret_cast<const double2 *>(L.csel[v]);
+        const uint2 lo = *reinterpret_cast<const uint2 *>(L.lo[v]);
+        c = c * cs.x;
+        c = c * ((S & lo.x) ? cs.y : 1.0);
+        const uint32_t rest = lo.y & S;
+        if (rest) {
+            const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+            for (uint32_t U = rest; U; U &= U - 1)
+                c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+        }
+    }
+    bsum = b;
+    cardS = c < 1.0 ? 1.0 : c;
+}
+
 template <int CM>
 __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t rank,
                                               uint32_t k, uint64_t off_k, const double *__restrict__ cost_km1,
                                               const double *__restrict__ card_km1) {
     constexpr int kPairBatch = 4;
-    // One pass over S: bsum = sum of C(s_i, i), and card(S) in card_of's
-    // order (members ascending, each card then the selectivities of its
-    // edges to smaller members, ascending).  The edge to v's lowest smaller
-    // neighbour comes from the (card, sel) pair of v (times an exact 1.0 when
-    // that neighbour is outside S); v's other smaller neighbours in S, which
-    // a tree seldom has, go through the sel row.  S's own colex rank comes
-    // with it from the filter.
-    double c = 1.0;
-    uint32_t bsum = 0;
-    {
-        uint32_t T = S;
-        for (uint32_t i = 0; i < k; ++i) {
-            const int v = ctz32(T);
-            T &= T - 1;
-            bsum += L.binom[v * 33 + i];
-            const double2 cs = *reinterpret_cast<const double2 *>(L.csel[v]);
-            const uint2 lo = *reinterpret_cast<const uint2 *>(L.lo[v]);
-            c = c * cs.x;
-            c = c * ((S & lo.x) ? cs.y : 1.0);
-            const uint32_t rest = lo.y & S;
-            if (rest) {
-                const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
-                for (uint32_t U = rest; U; U &= U - 1)
-                    c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
-            }
-        }
-    }
-    const double cardS = c < 1.0 ? 1.0 : c;
+    // S's own colex rank comes with it from the filter
+    uint32_t bsum;
+    double cardS;
+    tree_bsum_card(L, S, k, bsum, cardS);
     // C_out offers carry one operator, so the running best starts with it
     // and the operator never decides
     Key best = worst_key();
@@ -339,6 +352,95 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
         }
     }
     store_best(M, off_k + rank, best, cardS);
+}
+
+// eval_tree_set with the pairs of S spread over a group of P lanes (P
+// divides 64, groups are P consecutive lanes, all active together): lane
+// `sub` costs members sub, sub + P, ... (at most 32 / P of them, every
+// gather issued before any is used), then the group's keys are combined by
+// exchanges within the group and its first lane stores the entry.  Every
+// lane walks all k members for the colex ranks, so this pays only where a
+// level has too few sets to hide the gathers of a lane-per-set walk.
+template <int CM, int P>
+__device__ __forceinline__ void eval_tree_set_split(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t rank,
+                                                    uint32_t k, uint32_t sub, uint64_t off_k,
+                                                    const double *__restrict__ cost_km1,
+                                                    const double *__restrict__ card_km1) {
+    constexpr int kSlots = 32 / P;
+    uint32_t bsum;
+    double cardS;
+    tree_bsum_card(L, S, k, bsum, cardS);
+    uint32_t Av[kSlots], rk[kSlots];
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) Av[u] = rk[u] = 0u;
+    uint32_t pa = 0, pb = 0, T = S;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        if ((uint32_t)i < k) {
+            const int m = ctz32(T);
+            T &= T - 1;
+            pb += L.binom[m * 33 + i];
+            const uint32_t r = pa + (bsum - pb);  // colex rank of S - {m} at level k - 1
+            pa += L.binom[m * 33 + i + 1];
+            if ((uint32_t)(i % P) == sub && (S & L.pbit[m])) {
+                Av[i / P] = L.desc[m] & S;
+                rk[i / P] = r;
+            }
+        }
+    }
+    double cA[kSlots], cB[kSlots], kA[kSlots], kB[kSlots];
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const uint32_t A = Av[u];
+        if ((A & (A - 1)) == 0) {  // a singleton, or an empty slot (gathers entry 0)
+            cB[u] = cost_km1[rk[u]];
+            if (CM != MPDP_COST_COUT) kB[u] = card_km1[rk[u]];
+            const int m = ctz32(A | 0x80000000u);
+            cA[u] = L.bcost[m & 31];
+            kA[u] = L.card[m & 31];
+        } else {
+            const uint64_t ia = memo_index(L, A), ib = memo_index(L, S ^ A);
+            cA[u] = M.cost[ia];
+            cB[u] = M.cost[ib];
+            if (CM != MPDP_COST_COUT) {
+                kA[u] = M.card[ia];
+                kB[u] = M.card[ib];
+            }
+        }
+    }
+    Key best = worst_key();
+    if (CM == MPDP_COST_COUT) best.op = MPDP_OP_JOIN;
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const uint32_t A = Av[u], B = S ^ A;
+        const bool on = A != 0;
+        const double base = cA[u] + cB[u];
+        if (CM == MPDP_COST_COUT) {
+            offer_if<CM>(on, best, base + cardS, A < B ? A : B, MPDP_OP_JOIN);
+        } else {
+            const double out = 0.01 * cardS;
+            const double hjA = ((base + 0.0125 * kB[u]) + 0.0025 * kA[u]) + out;  // A outer, B hashed
+            const double nlA = (base + (0.0025 * kA[u]) * kB[u]) + out;
+            const double hjB = ((base + 0.0125 * kA[u]) + 0.0025 * kB[u]) + out;  // B outer, A hashed
+            const double nlB = (base + (0.0025 * kB[u]) * kA[u]) + out;
+            const bool hA = hjA <= nlA, hB = hjB <= nlB;
+            offer_if<CM>(on, best, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+            offer_if<CM>(on, best, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+        }
+    }
+    // a lane without pairs keeps the worst key, which never wins over a
+    // real offer; the key order is total, so the combining order is free
+#pragma unroll
+    for (int d = 1; d < P; d <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)best.c, d, P);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(best.c >> 32), d, P);
+        Key o;
+        o.c = ((unsigned long long)hi << 32) | lo;
+        o.l = (uint32_t)__shfl_xor((int)best.l, d, P);
+        o.op = (uint32_t)__shfl_xor((int)best.op, d, P);
+        if (key_less(o, best)) best = o;
+    }
+    if (sub == 0) store_best(M, off_k + rank, best, cardS);
 }
 
 
@@ -687,12 +789,6 @@ __device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoP
     store_best(M, memo_index(L, S), best, cardS);
 }
 
-__device__ __forceinline__ uint64_t memo_index_t(const uint32_t *binom, const uint64_t *loff, uint32_t T) {
-    uint32_t r = 0;
-    int i = 1;
-    for (uint32_t U = T; U; U &= U - 1, ++i) r += binom[ctz32(U) * 33 + i];
-    return loff[i - 1] + r;
-}
 
 
 
@@ -767,6 +863,31 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
     }
     wave_sync_lds();
     return tail;
+}
+
+// A small Alg. 2 level: groups of P lanes take one colex rank each (ranks
+// w * (64 / P) + group for w = w0, w0 + wstride, ... below wend); a group
+// whose candidate induces a tree costs it with eval_tree_set_split.  Lanes
+// of a group unrank and test the same candidate, so groups never diverge
+// inside.  Returns the number of connected sets it found (uniform across
+// the wave).
+template <int CM, int P>
+__device__ uint32_t level_tree_split_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
+                                          uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t lane) {
+    constexpr uint32_t kGroups = 64 / P;
+    const uint32_t group = lane / P, sub = lane % P;
+    const uint64_t off_k = L.loff[k], off_km1 = L.loff[k - 1];
+    const double *cost_km1 = M.cost + off_km1;
+    const double *card_km1 = M.card + off_km1;
+    uint32_t found = 0;
+    for (uint64_t w = w0; w < wend; w += wstride) {
+        const uint64_t r = w * kGroups + group;
+        const uint32_t S = r < ncand ? colex_unrank(L.binom, n, (int)k, (uint32_t)r) : 0u;
+        const bool tree = r < ncand && (uint32_t)popc32(S & children(L.ch, S)) == k - 1;
+        found += (uint32_t)__popcll(__ballot(tree && sub == 0));
+        if (tree) eval_tree_set_split<CM, P>(L, M, S, (uint32_t)r, k, sub, off_k, cost_km1, card_km1);
+    }
+    return found;
 }
 
 // One wave's share of the unrank + filter step for the block-based path:
@@ -873,14 +994,26 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
 // and wave 0 can walk the plan tree top-down one depth per round, every
 // node of the frontier reading its left set at once (the only dependent
 // chain is the tree's depth); then all `nthreads` threads fill cost, card
-// and operator of every node.  Returns false if the memo is inconsistent.
+// and operator of every node.  Memo indices are summed by the wave, one
+// member per lane, one frontier set at a time, and kept for the fill.
+// Returns false if the memo is inconsistent.
 struct PlanScratch {
+    uint64_t node_at[64];
     uint32_t node_set[64];
     int node_l[64], node_r[64];
     uint32_t fr_set[2][32];
     int fr_start[2][32];
     int error;
 };
+
+// Memo index of S from binom and loff alone, summed over the wave (every
+// lane active): lane v < 32 adds the term of relation v.
+__device__ __forceinline__ uint64_t memo_index_wave_t(const uint32_t *binom, const uint64_t *loff, uint32_t S,
+                                                      uint32_t lane) {
+    uint32_t term = 0;
+    if (lane < 32 && ((S >> lane) & 1u)) term = binom[lane * 33 + popc32(S & ((1u << lane) - 1u)) + 1];
+    return loff[popc32(S)] + wave_sum32(term);
+}
 
 __device__ bool extract_plan(const uint32_t *binom, const uint64_t *loff, const MemoPtrs &M, uint32_t n,
                              mpdp_plan_node *plan, double *root_cost, PlanScratch &P, uint32_t t,
@@ -895,16 +1028,24 @@ __device__ bool extract_plan(const uint32_t *binom, const uint64_t *loff, const 
             P.fr_start[0][0] = 0;
         }
         wave_sync_lds();
+        // the root's cost is read while the walk goes on
+        const uint64_t root_at = memo_index_wave_t(binom, loff, full, lane);
+        const double root_c = lane == 0 ? M.cost[root_at] : 0.0;
         int cur = 0;
         uint32_t nfr = n > 1 ? 1u : 0u;  // frontier size, uniform; at most 31 join nodes per depth
         bool bad = false;
         for (uint32_t depth = 0; nfr != 0 && depth < n; ++depth) {
+            uint64_t my_at = 0;  // lane j: index of frontier set j
+            for (uint32_t j = 0; j < nfr; ++j) {
+                const uint64_t at = memo_index_wave_t(binom, loff, P.fr_set[cur][j], lane);
+                if (lane == j) my_at = at;
+            }
             uint32_t push = 0, c0 = 0, c1 = 0;  // join children to visit next: c0, then c1
             int s0 = 0, s1 = 0;
             if (lane < nfr) {
                 const uint32_t S = P.fr_set[cur][lane];
                 const int st = P.fr_start[cur][lane];
-                const uint32_t Lft = M.left[memo_index_t(binom, loff, S)];
+                const uint32_t Lft = M.left[my_at];
                 if (Lft == 0 || (Lft & ~S) != 0 || Lft == S) {
                     bad = true;
                 } else {
@@ -913,6 +1054,7 @@ __device__ bool extract_plan(const uint32_t *binom, const uint64_t *loff, const 
                     const int rst = st + nl - 1;
                     const int idx = (int)n + st + popc32(S) - 2;
                     P.node_set[idx] = S;
+                    P.node_at[idx] = my_at;
                     P.node_l[idx] = nl >= 2 ? (int)n + st + nl - 2 : ctz32(Lft);
                     P.node_r[idx] = nr >= 2 ? (int)n + rst + nr - 2 : ctz32(Rgt);
                     if (nl >= 2) { c0 = Lft; s0 = st; push = 1; }
@@ -942,7 +1084,7 @@ __device__ bool extract_plan(const uint32_t *binom, const uint64_t *loff, const 
         }
         if (nfr != 0) bad = true;
         if (__ballot(bad) != 0ull && lane == 0) P.error = 1;
-        if (lane == 0) *root_cost = M.cost[memo_index_t(binom, loff, full)];
+        if (lane == 0) *root_cost = root_c;
     }
     __syncthreads();
     if (P.error) return false;
@@ -951,7 +1093,7 @@ __device__ bool extract_plan(const uint32_t *binom, const uint64_t *loff, const 
         plan[v] = mpdp_plan_node{-1, -1, 1u << v, MPDP_OP_SCAN, M.cost[at], M.card[at]};
     }
     for (uint32_t j = n + t; j + 1 < 2 * n; j += nthreads) {
-        const uint64_t at = memo_index_t(binom, loff, P.node_set[j]);
+        const uint64_t at = P.node_at[j];
         plan[j] = mpdp_plan_node{P.node_l[j], P.node_r[j], P.node_set[j], (uint32_t)M.op[at], M.cost[at], M.card[at]};
     }
     return true;

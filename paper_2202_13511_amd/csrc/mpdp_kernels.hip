@@ -37,6 +37,25 @@ __global__ void k_init(const DevGraph *g, uint32_t n, MemoPtrs M, Counters *cnt)
     for (uint32_t i = t; i < sizeof(Counters) / 4; i += blockDim.x) words[i] = 0;
 }
 
+// The ranges of nw wave-sized pieces of a level that this wave walks (w0,
+// w0 + ws, ... below we).  Workgroups are dealt to the eight XCDs round
+// robin (workgroup b runs on XCD b mod 8).  When the grid divides evenly,
+// each XCD sweeps its own contiguous eighth of the level's ranks, so the
+// neighbouring colex ranks of level k-1 that those sets gather sit in one
+// XCD's L2.
+__device__ __forceinline__ void wave_ranges(uint64_t nw, uint64_t &w0, uint64_t &ws, uint64_t &we) {
+    if (gridDim.x & 7u) {
+        w0 = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+        ws = (uint64_t)gridDim.x * kWaves;
+        we = nw;
+    } else {
+        const uint64_t x = blockIdx.x & 7u;
+        w0 = nw * x / 8 + (uint64_t)(blockIdx.x >> 3) * kWaves + (threadIdx.x >> 6);
+        ws = (uint64_t)(gridDim.x >> 3) * kWaves;
+        we = nw * (x + 1) / 8;
+    }
+}
+
 // One DP level of a tree join graph, Alg. 5's unrank, filter, evaluate,
 // prune and scatter fused.  Each wave walks ranges of 64 * kTreeChunk colex
 // ranks (kTreeChunk consecutive ranks per lane: unrank the first, then the
@@ -55,24 +74,29 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t per_wave = 64ull * kTreeChunk;
-    const uint64_t nw = (ncand + per_wave - 1) / per_wave;
-    // Workgroups are dealt to the eight XCDs round robin (workgroup b runs on
-    // XCD b mod 8).  When the grid divides evenly, each XCD sweeps its own
-    // contiguous eighth of the level's ranks, so the neighbouring colex ranks
-    // of level k-1 that those sets gather sit in one XCD's L2.
     uint64_t w0, ws, we;
-    if (gridDim.x & 7u) {
-        w0 = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-        ws = (uint64_t)gridDim.x * kWaves;
-        we = nw;
-    } else {
-        const uint64_t x = blockIdx.x & 7u;
-        w0 = nw * x / 8 + (uint64_t)(blockIdx.x >> 3) * kWaves + (threadIdx.x >> 6);
-        ws = (uint64_t)(gridDim.x >> 3) * kWaves;
-        we = nw * (x + 1) / 8;
-    }
+    wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
     const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact>(
         L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_rank_all[threadIdx.x >> 6], lane);
+    if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
+}
+
+// A small level of a tree join graph (few candidates, many members per set):
+// the same fused steps with kTreeSplitLanes lanes per candidate, so that
+// the pairs of a set are gathered at once instead of one lane's batches in
+// a row.
+template <int CM>
+__global__ __launch_bounds__(kBlock) void k_level_tree_split(const DevGraph *g, uint32_t k, uint64_t ncand,
+                                                             Counters *cnt, MemoPtrs M) {
+    __shared__ __align__(16) unsigned char lds_tree[kTreeLdsBytes];
+    stage_graph_prefix(g, lds_tree, kTreeLdsBytes);
+    const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
+    const uint32_t lane = threadIdx.x & 63u;
+    constexpr uint64_t per_wave = 64 / kTreeSplitLanes;
+    uint64_t w0, ws, we;
+    wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
+    const uint32_t found =
+        level_tree_split_wave<CM, kTreeSplitLanes>(L, M, (int)g->n, k, ncand, w0, ws, we, lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
 
@@ -203,6 +227,18 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
     // spread over some thousands of waves; a persistent-sized grid on large
     // ones, so each workgroup stages the query information once.
     constexpr uint64_t kWantWaves = 1024;
+    if (compact && k >= kTreeSplitMinK && ncand <= kTreeSplitMaxCand) {
+        const uint64_t per_block = (uint64_t)kWaves * (64 / kTreeSplitLanes);
+        uint64_t blocks = (ncand + per_block - 1) / per_block;
+        const uint32_t grid = (uint32_t)(blocks > kPersistGrid ? kPersistGrid : blocks);
+        if (cost_model == MPDP_COST_COUT)
+            hipLaunchKernelGGL(k_level_tree_split<MPDP_COST_COUT>, dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt,
+                               memo);
+        else
+            hipLaunchKernelGGL(k_level_tree_split<MPDP_COST_PGLIKE>, dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt,
+                               memo);
+        return hipGetLastError();
+    }
     const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > kPersistGrid ? kPersistGrid : blocks));
