@@ -18,6 +18,10 @@ constexpr int kFilterChunk = 16;    // consecutive ranks per lane in k_filter (<
 constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tree (1, 2 or 4)
 constexpr int kRing = 384;          // per-wave ring of connected sets (>= 63 + 64 * kTreeChunkMax)
 constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
+// Tree levels under C_out gather one word per pair: three workgroups per CU
+// leave fewer gathers in flight and lose fewer of them from the caches
+// (PG-like's two words per pair want the fourth).
+constexpr uint32_t kPersistGridCout = 768;
 // Tree levels with at least kTreeSplitMinK members per set (two or more
 // batches of gathers for one lane) and at most kTreeSplitMaxCand candidates
 // are too small to hide a lane's serial gathers: kTreeSplitLanes lanes take

@@ -241,7 +241,8 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
     }
     const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
-    const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > kPersistGrid ? kPersistGrid : blocks));
+    const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
+    const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
 #define MPDP_LEVEL_TREE(CMV, CH)                                                                        \
     do {                                                                                                \
         if (compact)                                                                                    \
