@@ -8,7 +8,12 @@
 // light set, the whole workgroup per heavy set), rebuilds the plan and
 // records the device wall clock at the query's start and end.  Memo and
 // scratch live in a per-workgroup slot that is reused from query to query,
-// so the workspace does not grow with the batch.
+// so the workspace does not grow with the batch.  A large cyclic query is
+// taken by a team of workgroups (consecutive queue entries): they split the
+// candidates and sets of every level and meet at device-wide barriers, in
+// the slot of the team's first member.  Entries are taken in queue order,
+// so a member waiting at a barrier waits only for workgroups that have
+// already taken their entries, or for ones that will take them next.
 #include <hip/hip_runtime.h>
 
 #include "mpdp_device.h"
@@ -19,6 +24,45 @@ namespace {
 
 constexpr int kBatchBlock = 512;
 constexpr int kBW = kBatchBlock / 64;
+constexpr unsigned long long kTeamWaitTicks = 200000000ull;  // 2 s of the 100 MHz device clock
+
+// The workgroups of a team meet here for the `phase`-th time.  Every wave
+// first waits until its own stores (memo, lists) have reached the L2; then
+// one thread per workgroup writes the L2 back (agent-scope release) and
+// arrives, and after the wait drops the lines other members may have
+// written from this CU's and this XCD's caches (agent-scope acquire), once
+// for all its waves.  The wait is bounded by the device clock: past
+// kTeamWaitTicks the team is marked failed, and every later wait of that
+// team returns at once.  Returns false once the team has failed; its
+// members then leave the query (its lists may be incomplete), and the
+// query reports an error.
+__device__ bool team_barrier(TeamRec *R, uint32_t team, uint32_t &phase, uint32_t &s_ok) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&R->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = team * (phase + 1u);
+        const unsigned long long start = wall_clock64();
+        while (__hip_atomic_load(&R->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+               __hip_atomic_load(&R->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            __builtin_amdgcn_s_sleep(2);
+            if ((unsigned long long)wall_clock64() - start > kTeamWaitTicks) {
+                __hip_atomic_store(&R->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        s_ok = __hip_atomic_load(&R->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    ++phase;
+    __syncthreads();
+    return s_ok != 0u;
+}
+
+__device__ __forceinline__ uint32_t load_shared_count(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Build the LDS image of one query inside the workgroup (everything except
 // the binomials, which are staged once per workgroup).
@@ -107,11 +151,11 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
 }
 
 template <int CM>
-__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_batch(const BatchQueryDev *qs, uint32_t nq, const uint32_t *edges,
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_batch(const BatchQueryDev *qs, const uint32_t *edges,
                                                        const double *cards, const double *sels,
                                                        const double *bcosts, const uint32_t *binom_g, char *slots, uint64_t slot_bytes,
                                                        uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
-                                                       BatchCounters *bc) {
+                                                       TeamRec *teams, BatchCounters *bc) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ uint32_t rings[kBW][kRing];
     __shared__ uint32_t ring_ranks[kBW][kRing];
@@ -119,23 +163,21 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
     __shared__ SetBlocks hsb;
     __shared__ Key hkeys[kBW];
     __shared__ PlanScratch P;
-    __shared__ uint32_t s_q, s_ntree, s_ngen, s_hcount, s_level;
+    __shared__ uint32_t s_q, s_ntree, s_ngen, s_hcount, s_level, s_ok;
     __shared__ unsigned long long s_conn, s_ccp, s_eval, s_t0;
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     if (t == 0) atomicMin(&bc->t0, (unsigned long long)wall_clock64());
+    // the entry count travels with the uploaded data, so a recorded launch
+    // serves any run with the same layout
+    const uint32_t nq = bc->entries;
     for (uint32_t i = t; i < 33 * 33; i += blockDim.x) L.binom[i] = binom_g[i];
 
-    // this workgroup's slot: memo (cost, card, left, op over 2^maxn entries), set list, heavy list
+    // a workgroup's slot: memo (cost, card, left, op over 2^maxn entries), set list, heavy list
     const uint64_t N = 1ull << maxn;
-    char *slot = slots + (uint64_t)blockIdx.x * slot_bytes;
-    MemoPtrs M{reinterpret_cast<double *>(slot), reinterpret_cast<double *>(slot + 8 * N),
-               reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
     const uint64_t list_off = (21 * N + 255) & ~255ull;
-    uint32_t *list = reinterpret_cast<uint32_t *>(slot + list_off);
     // sets of the widest level; read from global memory: the LDS copy of the
     // table is complete only after the first barrier below
     const uint32_t cap = binom_g[maxn * 33 + maxn / 2];
-    uint32_t *hv = list + cap;
 
     for (;;) {
         if (t == 0) s_q = atomicAdd(&bc->next, 1u);
@@ -143,6 +185,9 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
         const uint32_t q = s_q;
         if (q >= nq) break;
         const BatchQueryDev Q = qs[q];
+        const bool team = Q.team > 1;
+        TeamRec *R = team ? teams + Q.team_rec : nullptr;
+        uint32_t phase = 0;
         build_image(L, Q, edges, cards, sels, bcosts);
         const uint32_t n = Q.n;
         if (t == 0) {
@@ -151,16 +196,35 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
             s_ccp = 0;
             s_eval = 0;
         }
-        if (t < n) {
+        // a team works in its first member's slot, published through the team record
+        uint32_t slot_id = blockIdx.x;
+        if (team && Q.member == 0 && t == 0) __hip_atomic_store(&R->slot, slot_id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        char *slot = slots + (uint64_t)slot_id * slot_bytes;
+        MemoPtrs M{reinterpret_cast<double *>(slot), reinterpret_cast<double *>(slot + 8 * N),
+                   reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
+        if (t < n && Q.member == 0) {
             const uint64_t at = L.loff[1] + t;
             M.cost[at] = L.bcost[t];
             M.card[at] = L.card[t];
             M.left[at] = 0;
             M.op[at] = MPDP_OP_SCAN;
         }
-        __syncthreads();
+        bool failed = false;
+        if (team) {
+            failed = !team_barrier(R, Q.team, phase, s_ok);
+            slot_id = load_shared_count(&R->slot);
+            slot = slots + (uint64_t)slot_id * slot_bytes;
+            M = MemoPtrs{reinterpret_cast<double *>(slot), reinterpret_cast<double *>(slot + 8 * N),
+                         reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
+        } else {
+            __syncthreads();
+        }
+        uint32_t *list = reinterpret_cast<uint32_t *>(slot + list_off);
+        uint32_t *hv = list + cap;
+        // this workgroup's waves among the team's (w0, w0 + wstride, ...)
+        const uint32_t w0 = Q.member * kBW + wave, wstride = Q.team * kBW;
         unsigned long long my_ccp = 0, my_eval = 0;
-        for (uint32_t k = 2; k <= n; ++k) {
+        for (uint32_t k = 2; k <= n && !failed; ++k) {
             const uint64_t ncand = L.binom[n * 33 + k];
             if (Q.is_tree) {
                 if (t == 0) s_level = 0;
@@ -190,18 +254,31 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 __syncthreads();
                 continue;
             }
-            if (t == 0) { s_ntree = 0; s_ngen = 0; s_hcount = 0; }
+            uint32_t *ntp = team ? &R->ntree[k] : &s_ntree;
+            uint32_t *ngp = team ? &R->ngen[k] : &s_ngen;
+            uint32_t *nhp = team ? &R->nheavy[k] : &s_hcount;
+            if (!team && t == 0) { s_ntree = 0; s_ngen = 0; s_hcount = 0; }
             __syncthreads();
-            filter_wave(L, (int)n, k, ncand, wave, kBW, list, cap, &s_ntree, &s_ngen, lane);
-            __syncthreads();
-            const uint32_t count = s_ntree + s_ngen;
+            filter_wave(L, (int)n, k, ncand, w0, wstride, list, cap, ntp, ngp, lane);
+            if (team) {
+                if (!team_barrier(R, Q.team, phase, s_ok)) { failed = true; break; }
+            } else {
+                __syncthreads();
+            }
+            const uint32_t ntree = team ? load_shared_count(ntp) : s_ntree;
+            const uint32_t ngen = team ? load_shared_count(ngp) : s_ngen;
+            const uint32_t count = ntree + ngen;
             // light work: tree-inducing sets one per lane, other sets one per wave
-            light_sets<CM>(L, M, list, cap, s_ntree, s_ngen, wave, kBW, WS[wave], hv, &s_hcount, lane, my_ccp,
+            light_sets<CM>(L, M, list, cap, ntree, ngen, w0, wstride, WS[wave], hv, nhp, lane, my_ccp,
                            my_eval, false, (Q.sched >> kSchedHeavyShift) & 0xffffu);
-            __syncthreads();
-            // heavy sets: the whole workgroup each
-            const uint32_t hcount = s_hcount;
-            for (uint32_t h = 0; h < hcount; ++h) {
+            if (team) {
+                if (!team_barrier(R, Q.team, phase, s_ok)) { failed = true; break; }
+            } else {
+                __syncthreads();
+            }
+            // heavy sets: a whole workgroup each (a team deals them out)
+            const uint32_t hcount = team ? load_shared_count(nhp) : s_hcount;
+            for (uint32_t h = Q.member; h < hcount; h += Q.team) {
                 const uint32_t S = hv[h];
                 if (wave == 0) {
                     const SetBlocks sb = analyze_set(L, S, WS[0], lane, blockDim.x);
@@ -224,7 +301,9 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 __syncthreads();
             }
             if (t == 0) s_conn += count;
-            __syncthreads();
+            // the level's memo is complete before the next level reads it
+            if (team) failed = !team_barrier(R, Q.team, phase, s_ok);
+            else __syncthreads();
         }
         // counters of the block-based path
         for (int off = 32; off >= 1; off >>= 1) {
@@ -236,8 +315,21 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
             atomicAdd(&s_eval, my_eval);
         }
         __syncthreads();
+        if (team) {  // the team's counters meet in its record; the first member finishes the query
+            if (t == 0) {
+                __hip_atomic_fetch_add(&R->ccp, s_ccp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&R->evaluated, s_eval, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!failed) failed = !team_barrier(R, Q.team, phase, s_ok);
+            if (Q.member != 0) continue;
+            if (t == 0) {
+                s_ccp = __hip_atomic_load(&R->ccp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_eval = __hip_atomic_load(&R->evaluated, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
         double root = 0.0;
-        const bool ok = extract_plan(L.binom, L.loff, M, n, plans + Q.plan_off, &root, P, t, blockDim.x);
+        const bool ok = !failed && extract_plan(L.binom, L.loff, M, n, plans + Q.plan_off, &root, P, t, blockDim.x);
         __syncthreads();
         if (t == 0) {
             BatchOut o;
@@ -249,7 +341,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
             o.evaluated = s_eval;
             o.error = ok ? 0u : 1u;
             o.pad = 0;
-            out[q] = o;
+            out[Q.out] = o;
         }
         __syncthreads();
     }
@@ -257,17 +349,17 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
 
 }  // namespace
 
-hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs, uint32_t nq,
+hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs,
                         const uint32_t *edges, const double *cards, const double *sels, const double *bcosts,
                         const uint32_t *binom,
                         char *slots, uint64_t slot_bytes, uint32_t maxn, mpdp_plan_node *plans, BatchOut *out,
-                        BatchCounters *bc, hipStream_t s) {
+                        TeamRec *teams, BatchCounters *bc, hipStream_t s) {
     if (cost_model == MPDP_COST_COUT)
-        hipLaunchKernelGGL(k_batch<MPDP_COST_COUT>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, nq, edges, cards,
-                           sels, bcosts, binom, slots, slot_bytes, maxn, plans, out, bc);
+        hipLaunchKernelGGL(k_batch<MPDP_COST_COUT>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, edges, cards,
+                           sels, bcosts, binom, slots, slot_bytes, maxn, plans, out, teams, bc);
     else
-        hipLaunchKernelGGL(k_batch<MPDP_COST_PGLIKE>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, nq, edges,
-                           cards, sels, bcosts, binom, slots, slot_bytes, maxn, plans, out, bc);
+        hipLaunchKernelGGL(k_batch<MPDP_COST_PGLIKE>, dim3(workgroups), dim3(kBatchBlock), 0, s, qs, edges,
+                           cards, sels, bcosts, binom, slots, slot_bytes, maxn, plans, out, teams, bc);
     return hipGetLastError();
 }
 

@@ -328,14 +328,21 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
 
 // Internal flag for tests: run Alg. 3 (the general kernel) on tree joins too.
 constexpr uint32_t kFlagForceGeneral = 0x100u;
+constexpr uint32_t kFlagBatchAllTeams = 0x200u;  // test aid: every query that may take a team takes the largest
 
 // ---------------------------------------------------------------- batch
 
 struct BatchLayout {
-    size_t binom, counters, queries, edges, cards, sels, bcosts, plans, out, slots, slot_bytes, total;
-    uint32_t workgroups, maxn;
+    size_t binom, counters, queries, teams, edges, cards, sels, bcosts, plans, out, slots, slot_bytes, total;
+    uint32_t workgroups, maxn, max_teams, max_entries;
     uint64_t sum_m, sum_n, sum_nodes;
 };
+
+// Only a large cyclic query may be shared by a team of workgroups (a tree
+// query's sets are cheap and fill one workgroup well).  The layout depends
+// on the shapes alone, so it leaves room for every such query to take the
+// largest team; which ones do is decided per run from their edges.
+bool team_eligible(const mpdp_batch_query &Q) { return Q.n >= mpdp::kTeamMinRel && Q.m != Q.n - 1; }
 
 bool batch_layout(uint32_t nq, const mpdp_batch_query *qs, BatchLayout &B) {
     B = BatchLayout{};
@@ -349,11 +356,15 @@ bool batch_layout(uint32_t nq, const mpdp_batch_query *qs, BatchLayout &B) {
         B.sum_nodes += 2ull * qs[i].n - 1;
     }
     B.maxn = maxn;
-    B.workgroups = nq < mpdp::kBatchWorkgroups ? nq : mpdp::kBatchWorkgroups;
+    for (uint32_t i = 0; i < nq; ++i) B.max_teams += team_eligible(qs[i]) ? 1u : 0u;
+    B.max_entries = nq + (mpdp::kTeamSize - 1) * B.max_teams;
+    // every team fits at once: max_entries >= kTeamSize whenever a team may form
+    B.workgroups = B.max_entries < mpdp::kBatchWorkgroups ? B.max_entries : mpdp::kBatchWorkgroups;
     size_t o = 0;
     B.binom = o;    o = align_up(o + 33 * 33 * 4);
     B.counters = o; o = align_up(o + sizeof(mpdp::BatchCounters));
-    B.queries = o;  o = align_up(o + sizeof(mpdp::BatchQueryDev) * nq);
+    B.queries = o;  o = align_up(o + sizeof(mpdp::BatchQueryDev) * B.max_entries);
+    B.teams = o;    o = align_up(o + sizeof(mpdp::TeamRec) * B.max_teams);
     B.edges = o;    o = align_up(o + 8 * B.sum_m);
     B.cards = o;    o = align_up(o + 8 * B.sum_n);
     B.sels = o;     o = align_up(o + 8 * B.sum_m);
@@ -432,14 +443,78 @@ mpdp_status check_batch_args(uint32_t nq, const mpdp_batch_query *queries, const
     return MPDP_OK;
 }
 
-// Order in which the workgroups take the queries (larger queries first, ties
-// in input order) and each query's first plan node in input order.
-void batch_order(uint32_t nq, const mpdp_batch_query *queries, std::vector<uint32_t> &order,
-                 std::vector<uint64_t> &plan_at) {
+// Predicted device time (ms) of a query alone on one workgroup of the
+// batched kernel, for scheduling only.  Its connected sets are counted on a
+// breadth-first spanning tree from relation 0 (the subtrees of a rooted
+// tree: f(v) = prod over children of (1 + f(child)), summed over v).  A
+// tree query's time is close to linear in that count and in n^2; a cyclic
+// query's follows a power law in it and in 1 + its extra edges, and grows
+// exponentially with the size of
+// its 2-core (the relations left after repeatedly removing those of degree
+// one), which bounds the blocks Alg. 3 walks.  The coefficients were fitted
+// to measured per-query times of mixed batches of 8-20 relations on MI355X.
+double predicted_ms(const mpdp_batch_query &Q, const mpdp_edge *edges) {
+    const uint32_t n = Q.n;
+    uint32_t adj[32] = {0};
+    for (uint32_t e = 0; e < Q.m; ++e) {
+        const mpdp_edge E = edges[Q.edge_offset + e];
+        adj[E.u] |= 1u << E.v;
+        adj[E.v] |= 1u << E.u;
+    }
+    uint32_t order[32], parent[32], head = 0, tail = 0, seen = 1u;
+    order[tail++] = 0;
+    parent[0] = 0;
+    while (head < tail) {
+        const uint32_t v = order[head++];
+        for (uint32_t T = adj[v] & ~seen; T; T &= T - 1) {
+            const uint32_t c = (uint32_t)__builtin_ctz(T);
+            seen |= 1u << c;
+            parent[c] = v;
+            order[tail++] = c;
+        }
+    }
+    double f[32], subtrees = 0.0;
+    for (uint32_t i = 0; i < tail; ++i) f[order[i]] = 1.0;
+    for (uint32_t i = tail; i-- > 1;) f[parent[order[i]]] *= 1.0 + f[order[i]];
+    for (uint32_t i = 0; i < tail; ++i) subtrees += f[order[i]];
+    const uint32_t extra = Q.m - (n - 1);
+    if (extra == 0) return std::max(0.05, -0.361 + 1.20e-5 * subtrees + 0.00308 * (double)(n * n));
+    uint32_t alive = (n == 32) ? ~0u : (1u << n) - 1u;
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (uint32_t T = alive; T; T &= T - 1) {
+            const uint32_t v = (uint32_t)__builtin_ctz(T);
+            if (__builtin_popcount(adj[v] & alive) <= 1) {
+                alive &= ~(1u << v);
+                changed = true;
+            }
+        }
+    }
+    const double core = (double)__builtin_popcount(alive);
+    return std::exp(-6.466 + 0.1238 * core) * std::pow(subtrees, 0.856) * std::pow(1.0 + extra, 0.080);
+}
+
+// Team size of a query from its predicted time alone on one workgroup.
+uint32_t team_size(const mpdp_batch_query &Q, double ms) {
+    if (!team_eligible(Q)) return 1;
+    return ms >= 8.0 ? mpdp::kTeamSize : ms >= 3.0 ? mpdp::kTeamSize / 2 : 1u;
+}
+
+// Order in which the workgroups take the queries (longest predicted time
+// first, ties in input order), each query's team size in that order, and
+// each query's first plan node in input order.
+void batch_order(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,
+                 std::vector<uint32_t> &order, std::vector<uint32_t> &team, std::vector<uint64_t> &plan_at,
+                 bool all_teams = false) {
+    std::vector<double> ms(nq);
+    for (uint32_t i = 0; i < nq; ++i) ms[i] = predicted_ms(queries[i], edges);
     order.resize(nq);
     for (uint32_t i = 0; i < nq; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return queries[a].n > queries[b].n; });
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return ms[a] > ms[b]; });
+    team.resize(nq);
+    for (uint32_t j = 0; j < nq; ++j)
+        team[j] = all_teams ? (team_eligible(queries[order[j]]) ? mpdp::kTeamSize : 1u)
+                            : team_size(queries[order[j]], ms[order[j]]);
     plan_at.resize(nq);
     uint64_t p = 0;
     for (uint32_t i = 0; i < nq; ++i) { plan_at[i] = p; p += 2ull * queries[i].n - 1; }
@@ -448,14 +523,15 @@ void batch_order(uint32_t nq, const mpdp_batch_query *queries, std::vector<uint3
 // Host image of everything the batched kernel reads (B.plans bytes), to be
 // uploaded to the workspace in one copy.
 void fill_batch_upload(char *up, const BatchLayout &B, uint32_t nq, const mpdp_batch_query *queries,
-                       const std::vector<uint32_t> &order, const std::vector<uint64_t> &plan_at,
+                       const std::vector<uint32_t> &order, const std::vector<uint32_t> &team_of,
+                       const std::vector<uint64_t> &plan_at,
                        const mpdp_edge *edges, const double *cardinalities, const double *selectivities,
                        const double *base_costs, mpdp_cost_model cost_model, const mpdp_batch_schedule *sched) {
     std::memset(up, 0, B.plans);
     std::memcpy(up + B.binom, binom_table(), 33 * 33 * sizeof(uint32_t));
     auto *bc = reinterpret_cast<mpdp::BatchCounters *>(up + B.counters);
     bc->next = 0;
-    bc->pad = 0;
+    bc->entries = 0;
     bc->t0 = ~0ull;
     auto *dq = reinterpret_cast<mpdp::BatchQueryDev *>(up + B.queries);
     uint32_t *de = reinterpret_cast<uint32_t *>(up + B.edges);
@@ -463,13 +539,18 @@ void fill_batch_upload(char *up, const BatchLayout &B, uint32_t nq, const mpdp_b
     double *ds = reinterpret_cast<double *>(up + B.sels);
     double *db = reinterpret_cast<double *>(up + B.bcosts);
     uint64_t eo = 0, co = 0;
+    uint32_t entry = 0, team_rec = 0;
     for (uint32_t j = 0; j < nq; ++j) {
         const uint32_t i = order[j];
         const mpdp_batch_query &Q = queries[i];
         uint32_t packed = mpdp::kSchedDefault;
         if (sched) (void)encode_schedule(sched[i], packed);  // checked by check_batch_args
-        dq[j] = mpdp::BatchQueryDev{Q.n, Q.m, Q.m == Q.n - 1 ? 1u : 0u, (uint32_t)cost_model, co, eo, plan_at[i],
-                                    packed, 0u};
+        const uint32_t team = team_of[j];
+        for (uint32_t member = 0; member < team; ++member)
+            dq[entry++] = mpdp::BatchQueryDev{Q.n, Q.m, Q.m == Q.n - 1 ? 1u : 0u, (uint32_t)cost_model,
+                                              co, eo, plan_at[i], packed, j, team, member,
+                                              team > 1 ? team_rec : 0u, 0u};
+        if (team > 1) ++team_rec;
         for (uint32_t v = 0; v < Q.n; ++v) {
             dc[co + v] = cardinalities[Q.card_offset + v];
             db[co + v] = base_costs ? base_costs[Q.card_offset + v] : 0.0;
@@ -482,17 +563,20 @@ void fill_batch_upload(char *up, const BatchLayout &B, uint32_t nq, const mpdp_b
         co += Q.n;
         eo += Q.m;
     }
+    bc->entries = entry;  // at most B.max_entries: only eligible queries take teams
 }
 
 hipError_t enqueue_batch_kernel(char *base, const BatchLayout &B, uint32_t nq, mpdp_cost_model cost_model,
                                 bool with_bcosts, hipStream_t s) {
+    (void)nq;  // the kernel walks the queue entries, counted in the uploaded counters
     return mpdp::launch_batch(cost_model, B.workgroups, reinterpret_cast<mpdp::BatchQueryDev *>(base + B.queries),
-                              nq, reinterpret_cast<uint32_t *>(base + B.edges),
+                              reinterpret_cast<uint32_t *>(base + B.edges),
                               reinterpret_cast<double *>(base + B.cards), reinterpret_cast<double *>(base + B.sels),
                               with_bcosts ? reinterpret_cast<double *>(base + B.bcosts) : nullptr,
                               reinterpret_cast<uint32_t *>(base + B.binom), base + B.slots, B.slot_bytes, B.maxn,
                               reinterpret_cast<mpdp_plan_node *>(base + B.plans),
                               reinterpret_cast<mpdp::BatchOut *>(base + B.out),
+                              reinterpret_cast<mpdp::TeamRec *>(base + B.teams),
                               reinterpret_cast<mpdp::BatchCounters *>(base + B.counters), s);
 }
 
@@ -540,11 +624,11 @@ mpdp_status batch_core(uint32_t nq, const mpdp_batch_query *queries, const mpdp_
     if (ws_bytes < B.total) return MPDP_ENOMEM;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     char *base = static_cast<char *>(d_workspace);
-    std::vector<uint32_t> order;
+    std::vector<uint32_t> order, team;
     std::vector<uint64_t> plan_at;
-    batch_order(nq, queries, order, plan_at);
+    batch_order(nq, queries, edges, order, team, plan_at, (flags & kFlagBatchAllTeams) != 0);
     std::vector<char> up(B.plans);
-    fill_batch_upload(up.data(), B, nq, queries, order, plan_at, edges, cardinalities, selectivities, base_costs,
+    fill_batch_upload(up.data(), B, nq, queries, order, team, plan_at, edges, cardinalities, selectivities, base_costs,
                       cost_model, sched);
     const int rate_khz = wall_clock_khz();
     const bool timing = (flags & MPDP_FLAG_TIMING) != 0;
@@ -678,7 +762,7 @@ struct mpdp_batch_graph {
     mpdp_cost_model cm = MPDP_COST_COUT;
     std::vector<mpdp_batch_query> shape;  // n and m per query, offsets as given at creation
     BatchLayout B{};
-    std::vector<uint32_t> order;
+    std::vector<uint32_t> order, team;    // queue order and team sizes of the current run
     std::vector<uint64_t> plan_at;
     char *base = nullptr;                 // device workspace
     char *h_up = nullptr;                 // pinned: the upload image (B.plans bytes)
@@ -824,7 +908,6 @@ mpdp_status mpdp_batch_graph_create(uint32_t nq, const mpdp_batch_query *queries
         return MPDP_ENOMEM;
     }
     g->base = static_cast<char *>(d_workspace);
-    batch_order(nq, queries, g->order, g->plan_at);
     g->rate_khz = wall_clock_khz();
     const bool ok =
         hipHostMalloc(reinterpret_cast<void **>(&g->h_up), g->B.plans, hipHostMallocDefault) == hipSuccess &&
@@ -860,7 +943,10 @@ mpdp_status mpdp_batch_graph_run(mpdp_batch_graph *g, const mpdp_batch_query *qu
     const mpdp_status st0 = check_batch_args(g->nq, queries, edges, cardinalities, selectivities, nullptr, g->cm,
                                              schedules);
     if (st0 != MPDP_OK) return st0;
-    fill_batch_upload(g->h_up, g->B, g->nq, queries, g->order, g->plan_at, edges, cardinalities, selectivities,
+    // order and teams follow this run's edges; the layout, fixed by the
+    // shapes, has room for any choice of teams
+    batch_order(g->nq, queries, edges, g->order, g->team, g->plan_at);
+    fill_batch_upload(g->h_up, g->B, g->nq, queries, g->order, g->team, g->plan_at, edges, cardinalities, selectivities,
                       nullptr, g->cm, schedules);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     HIPCHK(hipGraphLaunch(g->exec, s));

@@ -70,12 +70,31 @@ struct Counters {
     unsigned long long ccp;       // unordered csg-cmp pairs (general path)
 };
 
-// Batched path (mpdp_batch.hip): one query per workgroup at a time.
+// Batched path (mpdp_batch.hip): one queue entry per workgroup at a time.
+// A query is one entry, or, if it is large and cyclic, kTeamSize entries in
+// a row: a team of workgroups that share its levels.
 struct BatchQueryDev {
     uint32_t n, m, is_tree, cost_model;
     uint64_t card_off, edge_off, plan_off;
-    uint32_t sched, pad;  // the query's schedule, packed as below
+    uint32_t sched, out;       // the query's schedule (packed as below); index of its BatchOut
+    uint32_t team, member;     // workgroups sharing the query (1: alone); this entry's place among them
+    uint32_t team_rec, pad;    // the team's TeamRec (team > 1)
 };
+
+// Shared state of one team, zero at the start of a launch.  The first
+// member publishes its memo slot, which the whole team uses; the level's
+// list counts live here instead of in LDS.
+struct TeamRec {
+    uint32_t arrive;                 // barrier arrivals so far
+    uint32_t slot;                   // workgroup whose slot holds the memo and lists
+    uint32_t error;                  // a barrier wait ran out of time
+    uint32_t pad;
+    uint32_t ntree[24], ngen[24], nheavy[24];  // per level k
+    unsigned long long ccp, evaluated;
+};
+
+constexpr uint32_t kTeamSize = 8;     // largest team
+constexpr uint32_t kTeamMinRel = 17;  // only cyclic queries of at least this many relations may get a team
 
 // Schedule of one query in the batched kernel: bits 0-1 hold log2 of the
 // consecutive ranks per lane of a tree query's levels (1, 2 or 4), bits
@@ -93,17 +112,19 @@ struct BatchOut {
 };
 
 struct BatchCounters {
-    uint32_t next, pad;      // next query to take
+    uint32_t next;           // next queue entry to take
+    uint32_t entries;        // queue entries of this launch
     unsigned long long t0;   // earliest workgroup start (device wall clock)
 };
 
 constexpr uint32_t kBatchMaxRel = 20;      // largest query the batched path takes
+static_assert(kBatchMaxRel < 24, "TeamRec holds the counts of levels up to 23");
 constexpr uint32_t kBatchWorkgroups = 512; // persistent workgroups (two per CU)
 
-hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs, uint32_t nq,
+hipError_t launch_batch(int cost_model, uint32_t workgroups, const BatchQueryDev *qs,
                         const uint32_t *edges, const double *cards, const double *sels, const double *bcosts,
                         const uint32_t *binom, char *slots, uint64_t slot_bytes, uint32_t maxn,
-                        mpdp_plan_node *plans, BatchOut *out,
+                        mpdp_plan_node *plans, BatchOut *out, TeamRec *teams,
                         BatchCounters *bc, hipStream_t s);
 
 hipError_t launch_init(const DevGraph *g, uint32_t n, MemoPtrs memo, Counters *cnt, hipStream_t s);

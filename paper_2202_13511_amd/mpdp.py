@@ -23,6 +23,7 @@ MPDP_OP_SCAN, MPDP_OP_HASH, MPDP_OP_NESTLOOP, MPDP_OP_JOIN = 0, 1, 2, 3
 MPDP_FLAG_TIMING = 1
 MPDP_FLAG_ABLATE_DPSUB, MPDP_FLAG_ABLATE_NO_COMPACTION = 2, 4
 _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
+_FLAG_BATCH_ALL_TEAMS = 0x200  # test aid: every batched query that may take a team of workgroups takes one
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
             "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_optimize_cpu", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",

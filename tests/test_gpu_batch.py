@@ -66,3 +66,45 @@ def test_batch_right_after_single_query_kernels():
         r = mpdp.mpdp_optimize_batch(qs, cm, ws)
         for q, c in zip(qs, r.costs):
             assert np.float64(c).view(np.uint64) == np.float64(oracle.mpdp(q, cm).root_cost).view(np.uint64), q.name
+
+
+def team_queries(count, seed):
+    """Cyclic queries of 19 and 20 relations: the batched kernel gives each
+    one a team of workgroups."""
+    out = [q for q in W.batch_mixed(6 * count, seed, n_range=(19, 20)) if q.m != q.n - 1]
+    assert len(out) >= count
+    return out[:count]
+
+
+@pytest.mark.parametrize("cm,all_teams", [(mpdp.MPDP_COST_COUT, True), (mpdp.MPDP_COST_PGLIKE, True),
+                                          (mpdp.MPDP_COST_COUT, False)], ids=["cout-all", "pglike-all", "cout"])
+def test_team_queries_match_single_calls(cm, all_teams):
+    """Large cyclic queries on teams of workgroups, among queries that run on
+    one workgroup each.  With every such query on a team of 8, 80 teams are
+    more than the 512 workgroups hold at once, so later teams form from
+    workgroups that finished earlier entries; without, teams of 4 and 8 go to
+    the queries predicted to be slow.  Costs and plans bit for bit, and the
+    summed counters, against single-query calls (themselves checked against
+    the oracle)."""
+    big = team_queries(80, 31)
+    queries = big + W.batch_mixed(200, 32, n_range=(6, 18))
+    ws = mpdp.batch_workspace(queries)
+    res = mpdp.mpdp_optimize_batch(queries, cm, ws, flags=mpdp._FLAG_BATCH_ALL_TEAMS if all_teams else 0)
+    conn = ccp = 0
+    for q, cost, plan in zip(queries, res.costs, res.plans):
+        one = mpdp.mpdp_optimize(q, cm)
+        assert np.float64(cost).view(np.uint64) == np.float64(one.cost).view(np.uint64), q.name
+        assert plan == one.plan, q.name
+        conn += one.stats["connected_sets"]
+        ccp += one.stats["ccp_pairs"]
+    assert res.stats["connected_sets"] == conn and res.stats["ccp_pairs"] == ccp
+    assert np.all(res.latency_us > 0)
+
+
+def test_batch_of_two_teams_against_oracle():
+    """Only team queries: 16 queue entries on 16 workgroups."""
+    queries = team_queries(2, 41)
+    ws = mpdp.batch_workspace(queries)
+    res = mpdp.mpdp_optimize_batch(queries, mpdp.MPDP_COST_COUT, ws, flags=mpdp._FLAG_BATCH_ALL_TEAMS)
+    assert res.stats["workgroups"] == 16
+    check_against_oracle(queries, res, mpdp.MPDP_COST_COUT)

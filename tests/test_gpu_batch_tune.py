@@ -23,7 +23,9 @@ def same(a, b, names):
 
 @pytest.mark.parametrize("cm", [mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE])
 def test_every_schedule_gives_the_default_result(cm):
-    queries = W.batch_mixed(160, 21, n_range=(6, 16)) + [W.clique(11, 2), W.cycle_chords(5, n=16, chords=6)]
+    # the last four are cyclic with 19 or 20 relations: teams of workgroups
+    big = [q for q in W.batch_mixed(40, 22, n_range=(19, 20)) if q.m != q.n - 1][:4]
+    queries = W.batch_mixed(160, 21, n_range=(6, 16)) + [W.clique(11, 2), W.cycle_chords(5, n=16, chords=6)] + big
     names = [q.name for q in queries]
     ws = mpdp.batch_workspace(queries)
     ref = mpdp.mpdp_optimize_batch(queries, cm, ws)
@@ -72,7 +74,8 @@ def restat(queries, seed):
 
 @pytest.mark.parametrize("cm", [mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE])
 def test_graph_replays_match_eager_launches(cm):
-    base = W.batch_mixed(300, 9, n_range=(6, 17))
+    big = [q for q in W.batch_mixed(60, 8, n_range=(19, 20)) if q.m != q.n - 1][:12]  # teams of workgroups
+    base = W.batch_mixed(300, 9, n_range=(6, 17)) + big
     # the same shape (n, m per query) with other topologies: a chain and a
     # star both have n - 1 edges
     swapped = [W.star(q.n, 77 + i) if (q.m == q.n - 1 and q.n >= 3 and i % 2) else q for i, q in enumerate(base)]
