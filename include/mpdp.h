@@ -211,14 +211,19 @@ typedef struct {
 
 /* Device workspace bytes for mpdp_optimize_batch (0 if a query is invalid in
  * size: n = 0 or n > 20).  It grows with the total input and output sizes
- * and with min(nq, 512) memo slots of 2^max_n entries, not with nq itself. */
+ * and with at most 512 memo slots of 2^max_n entries, not with nq itself
+ * (plus a few hundred bytes per cyclic query of 17 or more relations, which
+ * may be shared by a team of workgroups). */
 size_t mpdp_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries);
 
 /*
  * Optimize nq queries in one persistent launch on hip_stream: every
  * workgroup takes the next query, runs all its DP levels with workgroup
- * barriers between levels, and writes its plan.  Results equal those of
- * mpdp_optimize on each query alone.
+ * barriers between levels, and writes its plan.  A cyclic query of 17 or
+ * more relations that is predicted to be slow is taken by a team of 4 or 8
+ * workgroups, which split every level and meet at device-wide barriers
+ * (each wait bounded; a team that times out reports MPDP_EDEVICE).
+ * Results equal those of mpdp_optimize on each query alone.
  *   plans_out      host, sum over q of (2 n_q - 1) nodes; query q's plan
  *                  (layout of mpdp_plan_node) starts after those of 0..q-1
  *   costs_out      host, nq root costs
@@ -227,8 +232,10 @@ size_t mpdp_batch_workspace_bytes(uint32_t nq, const mpdp_batch_query *queries);
  *   start_us_out   host, nullable: per query, microseconds from the start of
  *                  the launch to the start of that query
  *   stats_out      host, nullable
- * Workgroups take the queries in order of decreasing size (more relations
- * first, ties in input order), which shortens the tail of the launch.
+ * Workgroups take the queries in order of decreasing predicted time (from
+ * the query's shape: its relations, extra edges, the connected subsets of a
+ * spanning tree and the size of its 2-core; ties in input order), which
+ * shortens the tail of the launch.
  * Validation is done on the host before any HIP call (MPDP_EINVAL,
  * MPDP_ENOTCONNECTED, MPDP_ETOOLARGE name the first failing query's error);
  * the call waits for hip_stream before returning.
