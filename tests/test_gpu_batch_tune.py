@@ -79,7 +79,12 @@ def test_graph_replays_match_eager_launches(cm):
     # the same shape (n, m per query) with other topologies: a chain and a
     # star both have n - 1 edges
     swapped = [W.star(q.n, 77 + i) if (q.m == q.n - 1 and q.n >= 3 and i % 2) else q for i, q in enumerate(base)]
-    data = [base, restat(base, 1), swapped, restat(swapped, 2), base]
+    # the large cyclic queries become rings with chords of the same n and m:
+    # another predicted time, so other teams of workgroups in the same layout
+    rings = [W.cycle_chords(90 + i, n=q.n, chords=q.m - q.n) if (q.n >= 19 and q.m > q.n) else q
+             for i, q in enumerate(swapped)]
+    assert [(q.n, q.m) for q in rings] == [(q.n, q.m) for q in base]
+    data = [base, restat(base, 1), swapped, restat(swapped, 2), rings, base]
     ws = mpdp.batch_workspace(base)
     g = mpdp.BatchGraph(base, cm, ws)
     sched = [((1, 2, 4)[i % 3], 64 if i % 2 else 256) for i in range(len(base))]
