@@ -163,7 +163,8 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
     __shared__ SetBlocks hsb;
     __shared__ Key hkeys[kBW];
     __shared__ PlanScratch P;
-    __shared__ uint32_t s_q, s_ntree, s_ngen, s_hcount, s_level, s_ok;
+    __shared__ uint32_t s_q, s_level, s_ok;
+    __shared__ uint32_t s_ntree[24], s_ngen[24], s_nheavy[24];  // per level k: list and heavy-list counts
     __shared__ unsigned long long s_conn, s_ccp, s_eval, s_t0;
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     if (t == 0) atomicMin(&bc->t0, (unsigned long long)wall_clock64());
@@ -202,6 +203,11 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
         char *slot = slots + (uint64_t)slot_id * slot_bytes;
         MemoPtrs M{reinterpret_cast<double *>(slot), reinterpret_cast<double *>(slot + 8 * N),
                    reinterpret_cast<uint32_t *>(slot + 16 * N), reinterpret_cast<uint8_t *>(slot + 20 * N)};
+        if (t < 24) {
+            s_ntree[t] = 0;
+            s_ngen[t] = 0;
+            s_nheavy[t] = 0;
+        }
         if (t < n && Q.member == 0) {
             const uint64_t at = L.loff[1] + t;
             M.cost[at] = L.bcost[t];
@@ -219,10 +225,22 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
         } else {
             __syncthreads();
         }
-        uint32_t *list = reinterpret_cast<uint32_t *>(slot + list_off);
-        uint32_t *hv = list + cap;
+        // two set lists of cap entries (level k uses list k mod 2, so the
+        // filter of level k + 1 can run with level k's evaluation), then the
+        // heavy list
+        uint32_t *lists = reinterpret_cast<uint32_t *>(slot + list_off);
+        uint32_t *hv = lists + 2 * cap;
         // this workgroup's waves among the team's (w0, w0 + wstride, ...)
         const uint32_t w0 = Q.member * kBW + wave, wstride = Q.team * kBW;
+        auto filter_level = [&](uint32_t kk) {  // connected sets of level kk into their list
+            filter_wave(L, (int)n, kk, L.binom[n * 33 + kk], w0, wstride, lists + (kk & 1u) * cap, cap,
+                        team ? &R->ntree[kk] : &s_ntree[kk], team ? &R->ngen[kk] : &s_ngen[kk], lane);
+        };
+        if (!Q.is_tree && n >= 2 && !failed) {
+            filter_level(2);
+            if (team) failed = !team_barrier(R, Q.team, phase, s_ok);
+            else __syncthreads();
+        }
         unsigned long long my_ccp = 0, my_eval = 0;
         for (uint32_t k = 2; k <= n && !failed; ++k) {
             const uint64_t ncand = L.binom[n * 33 + k];
@@ -254,30 +272,22 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 __syncthreads();
                 continue;
             }
-            uint32_t *ntp = team ? &R->ntree[k] : &s_ntree;
-            uint32_t *ngp = team ? &R->ngen[k] : &s_ngen;
-            uint32_t *nhp = team ? &R->nheavy[k] : &s_hcount;
-            if (!team && t == 0) { s_ntree = 0; s_ngen = 0; s_hcount = 0; }
-            __syncthreads();
-            filter_wave(L, (int)n, k, ncand, w0, wstride, list, cap, ntp, ngp, lane);
-            if (team) {
-                if (!team_barrier(R, Q.team, phase, s_ok)) { failed = true; break; }
-            } else {
-                __syncthreads();
-            }
-            const uint32_t ntree = team ? load_shared_count(ntp) : s_ntree;
-            const uint32_t ngen = team ? load_shared_count(ngp) : s_ngen;
+            // level k's list was filtered during level k - 1 (or before the loop)
+            uint32_t *nhp = team ? &R->nheavy[k] : &s_nheavy[k];
+            const uint32_t ntree = team ? load_shared_count(&R->ntree[k]) : s_ntree[k];
+            const uint32_t ngen = team ? load_shared_count(&R->ngen[k]) : s_ngen[k];
             const uint32_t count = ntree + ngen;
             // light work: tree-inducing sets one per lane, other sets one per wave
-            light_sets<CM>(L, M, list, cap, ntree, ngen, w0, wstride, WS[wave], hv, nhp, lane, my_ccp,
-                           my_eval, false, (Q.sched >> kSchedHeavyShift) & 0xffffu);
+            light_sets<CM>(L, M, lists + (k & 1u) * cap, cap, ntree, ngen, w0, wstride, WS[wave], hv, nhp, lane,
+                           my_ccp, my_eval, false, (Q.sched >> kSchedHeavyShift) & 0xffffu);
+            if (k < n) filter_level(k + 1);
             if (team) {
                 if (!team_barrier(R, Q.team, phase, s_ok)) { failed = true; break; }
             } else {
                 __syncthreads();
             }
             // heavy sets: a whole workgroup each (a team deals them out)
-            const uint32_t hcount = team ? load_shared_count(nhp) : s_hcount;
+            const uint32_t hcount = team ? load_shared_count(nhp) : s_nheavy[k];
             for (uint32_t h = Q.member; h < hcount; h += Q.team) {
                 const uint32_t S = hv[h];
                 if (wave == 0) {

@@ -372,7 +372,7 @@ bool batch_layout(uint32_t nq, const mpdp_batch_query *qs, BatchLayout &B) {
     B.plans = o;    o = align_up(o + sizeof(mpdp_plan_node) * B.sum_nodes);
     B.out = o;      o = align_up(o + sizeof(mpdp::BatchOut) * nq);
     const uint64_t N = 1ull << maxn;
-    B.slot_bytes = align_up(21 * N) + align_up(8 * binom64(maxn, maxn / 2));
+    B.slot_bytes = align_up(21 * N) + align_up(12 * binom64(maxn, maxn / 2));  // memo, two set lists, heavy list
     B.slots = o;    o += B.slot_bytes * B.workgroups;
     B.total = align_up(o);
     return true;
