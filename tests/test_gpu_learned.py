@@ -84,7 +84,7 @@ def test_trained_scorer_against_plain_uniondp():
     """Train the scorer on the GPU (teacher round, then DAgger rounds on the
     network's own unions; plans of 20-26 relations from the exact DP) and
     measure what it gains over plain UnionDP on held-out queries, with the
-    exact DP as the judge: geometric-mean ratio to the optimum at k = 15
+    exact DP as the reference: geometric-mean ratio to the optimum at k = 15
     under C_out.  The run is deterministic (fixed draws, no atomics in the
     gradient sums), so the comparison is stable."""
     from paper_2202_13511_amd import scorer
