@@ -173,3 +173,14 @@ def test_batch_schedule_tuner_and_graph_validation_without_gpu():
     assert lib.mpdp_batch_graph_run(None, qs, ep, c.ctypes.data_as(f64p), s.ctypes.data_as(f64p), None, None,
                                     plans, costs.ctypes.data_as(f64p), None, None) == mpdp.MPDP_EINVAL
     lib.mpdp_batch_graph_destroy(None)
+
+
+def test_batch_workspace_leaves_room_for_teams():
+    """A cyclic query of 17 or more relations may be shared by a team of up
+    to 8 workgroups, so the batch workspace holds 7 more queue entries of 64
+    bytes and a team record for it; a tree of the same size, or a smaller
+    cyclic query, needs none (their edge arrays differ by one edge only)."""
+    base = [W.chain(10, s) for s in range(20)]
+    size = lambda q: mpdp.mpdp_batch_workspace_bytes(base + [q])
+    assert size(W.cycle(18, 1)) - size(W.chain(18, 1)) >= 7 * 64
+    assert size(W.cycle(16, 1)) - size(W.chain(16, 1)) < 7 * 64
