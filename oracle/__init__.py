@@ -43,7 +43,7 @@ def build(force: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp",
                                "-shared", "-fPIC", "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB
@@ -66,6 +66,8 @@ def lib():
         L.oracle_dpsub.restype = i
         L.oracle_mpdp.argtypes = memo_sig + [i] + out_sig
         L.oracle_mpdp.restype = i
+        L.oracle_mpdp_threads.argtypes = memo_sig + [i, i] + out_sig
+        L.oracle_mpdp_threads.restype = i
         L.oracle_mpdp_bc.argtypes = memo_sig + [f64p] + out_sig
         L.oracle_mpdp_bc.restype = i
         L.oracle_dpccp.argtypes = memo_sig + out_sig
@@ -145,16 +147,19 @@ def dpsub(q, cost_model=COST_COUT) -> Memo:
     return _run(lib().oracle_dpsub, q, cost_model)
 
 
-def mpdp(q, cost_model=COST_COUT, force_general=False) -> Memo:
+def mpdp(q, cost_model=COST_COUT, force_general=False, threads=1) -> Memo:
     """MPDP: Alg. 2 when the join graph is a tree, else Alg. 3 (n <= 30).
     A query with ``base_cost`` set treats relation v as an intermediate
-    result whose plan costs base_cost[v]."""
+    result whose plan costs base_cost[v].  ``threads`` > 1 splits the sets
+    of each level over that many threads (same memo and counters)."""
     bc = getattr(q, "base_cost", None)
     if bc is not None:
-        if force_general:
-            raise ValueError("force_general is not combined with base costs")
+        if force_general or threads != 1:
+            raise ValueError("force_general and threads are not combined with base costs")
         b = np.ascontiguousarray(bc, dtype=np.float64)
         return _run(lib().oracle_mpdp_bc, q, cost_model, _p(b, ctypes.c_double))
+    if threads != 1:
+        return _run(lib().oracle_mpdp_threads, q, cost_model, int(bool(force_general)), int(threads))
     return _run(lib().oracle_mpdp, q, cost_model, int(bool(force_general)))
 
 

@@ -11,7 +11,7 @@
  *
  * Definitions (readings of the paper, each stated once here):
  *
- *  card(S)  The paper never specifies cardinality estimation (Section 6.1,
+ *  card(S)  The paper never specifies cardinality estimation (Section 7.1,
  *           cost model paragraph).  card(S) is a function of S alone:
  *             c = 1.0
  *             for v in S ascending:
@@ -19,11 +19,11 @@
  *                 for u in S, u < v, (u,v) an edge, ascending: c = c * sel(u,v)
  *             card(S) = (c < 1.0) ? 1.0 : c
  *
- *  C_out    (Section 6.1, after Neumann 2018) cost({v}) = 0,
+ *  C_out    (Section 7.1, after Neumann 2018) cost({v}) = 0,
  *           cost(L join R) = (cost(L) + cost(R)) + card(L u R).
  *
  *  PG-like  The paper's PostgreSQL-like model has no published formulas
- *           (Section 6.1).  Our own, from PostgreSQL's default constants
+ *           (Section 7.1).  Our own, from PostgreSQL's default constants
  *           cpu_tuple_cost = 0.01 and cpu_operator_cost = 0.0025:
  *             cost({v}) = 0.01 * card[v]
  *             HJ(L,R) = (((cL + cR) + 0.0125 * card(R)) + 0.0025 * card(L)) + 0.01 * card(S)
@@ -330,7 +330,7 @@ static int graph_is_tree(const og *g, int m)
 }
 
 static int mpdp_run(og *gp, int m, int force_general, double *mcost, double *mcard, uint32_t *mleft,
-                    uint8_t *mop, uint64_t *counters);
+                    uint8_t *mop, uint64_t *counters, int nthreads);
 
 int oracle_mpdp(int n, int m, const uint32_t *edges, const double *card, const double *sel,
                 int cost_model, int force_general, double *mcost, double *mcard, uint32_t *mleft,
@@ -338,7 +338,17 @@ int oracle_mpdp(int n, int m, const uint32_t *edges, const double *card, const d
 {
     og g;
     if (n > 30 || og_build(&g, n, m, edges, card, sel, cost_model)) return -1;
-    return mpdp_run(&g, m, force_general, mcost, mcard, mleft, mop, counters);
+    return mpdp_run(&g, m, force_general, mcost, mcard, mleft, mop, counters, 1);
+}
+
+/* oracle_mpdp with the sets of each level split over nthreads threads. */
+int oracle_mpdp_threads(int n, int m, const uint32_t *edges, const double *card, const double *sel,
+                        int cost_model, int force_general, int nthreads, double *mcost, double *mcard,
+                        uint32_t *mleft, uint8_t *mop, uint64_t *counters)
+{
+    og g;
+    if (n > 30 || og_build(&g, n, m, edges, card, sel, cost_model)) return -1;
+    return mpdp_run(&g, m, force_general, mcost, mcard, mleft, mop, counters, nthreads);
 }
 
 /* MPDP where every relation carries the cost of its plan (bcost[v]): the
@@ -352,11 +362,80 @@ int oracle_mpdp_bc(int n, int m, const uint32_t *edges, const double *card, cons
     if (n > 30 || og_build(&g, n, m, edges, card, sel, cost_model)) return -1;
     g.has_bcost = 1;
     for (int v = 0; v < n; v++) g.bcost[v] = bcost[v];
-    return mpdp_run(&g, m, 0, mcost, mcard, mleft, mop, counters);
+    return mpdp_run(&g, m, 0, mcost, mcard, mleft, mop, counters, 1);
 }
 
+/* Evaluate one set S of the current level: skip it if G[S] is not
+ * connected, else find its best plan from memo entries of smaller sets. */
+static void mpdp_set(const og *g, omemo *M, int tree, uint32_t S, ocount *C)
+{
+    if (!connected(g, S)) return;
+    C->connected_sets++;
+    double cardS = card_of(g, S);
+    best_t b = {0, 0, 0, 0};
+    if (tree) {
+        /* Alg. 2: one join pair per edge of the tree G[S]; both
+           orientations of each pair are costed. */
+        for (uint32_t T = S; T; T &= T - 1) {
+            int v = lowest(T);
+            for (uint32_t U = g->adj[v] & S & below(v); U; U &= U - 1) {
+                int u = lowest(U);
+                uint32_t L = grow(g, bit(u), S & ~bit(v));
+                uint32_t R = S & ~L;
+                C->evaluated += 2;
+                C->ccp_ordered += 2;
+                consider(g, M, L, R, cardS, &b);
+                consider(g, M, R, L, cardS, &b);
+            }
+        }
+    } else {
+        /* Alg. 3: vertex-based enumeration inside each block, then
+           grow the block pair to a pair of S. */
+        uint32_t blocks[32];
+        int nb = find_blocks(g, S, blocks);
+        for (int k = 0; k < nb; k++) {
+            uint32_t blk = blocks[k];
+            for (uint32_t lb = (0u - blk) & blk; lb != 0; lb = (lb - blk) & blk) {
+                if (lb == blk) continue; /* proper, non-empty subsets only */
+                C->evaluated++;
+                uint32_t rb = blk & ~lb;
+                if (rb == 0 || lb == 0) continue;
+                if (!connected(g, lb)) continue;
+                if (!connected(g, rb)) continue;
+                if ((rb & lb) != 0) continue;
+                if (!adjacent(g, lb, rb)) continue;
+                C->ccp_ordered++;
+                uint32_t L = grow(g, lb, S & ~rb);
+                uint32_t R = S & ~L;
+                consider(g, M, L, R, cardS, &b);
+            }
+        }
+    }
+    memo_store(M, S, &b, cardS);
+}
+
+/* Every i-subset of the n relations whose top `hi` relations (n - hi and
+ * up) are exactly the pattern h: the low part walks the subsets of the
+ * remaining relations with the remaining popcount. */
+static void mpdp_part(const og *g, omemo *M, int tree, int i, int hi, uint32_t h, ocount *C)
+{
+    int n = g->n, lo = n - hi, want = i - __builtin_popcount(h);
+    if (want < 0 || want > lo) return;
+    uint32_t top = lo >= 32 ? 0u : h << lo;
+    if (want == 0) { mpdp_set(g, M, tree, top, C); return; }
+    uint64_t last = (uint64_t)1 << lo;
+    for (uint64_t l = below(want); l < last; l = next_same_popcount((uint32_t)l)) {
+        mpdp_set(g, M, tree, top | (uint32_t)l, C);
+        if (l == ((uint64_t)below(want) << (lo - want))) break; /* the last i-subset of the low part */
+    }
+}
+
+/* The level loop (Section 5, Alg. 5): sets of one size depend only on
+ * smaller sets, so with nthreads > 1 the sets of a level are split by the
+ * pattern of their top relations and evaluated in parallel.  The memo and
+ * the counters are the same whatever nthreads is. */
 static int mpdp_run(og *gp, int m, int force_general, double *mcost, double *mcard, uint32_t *mleft,
-                    uint8_t *mop, uint64_t *counters)
+                    uint8_t *mop, uint64_t *counters, int nthreads)
 {
     og g = *gp;
     int n = g.n;
@@ -364,53 +443,17 @@ static int mpdp_run(og *gp, int m, int force_general, double *mcost, double *mca
     ocount C = {0, 0, 0};
     memo_init(&g, &M);
     int tree = !force_general && graph_is_tree(&g, m);
+    int hi = nthreads > 1 ? (n < 10 ? n : 10) : 0;
     for (int i = 2; i <= n; i++) {
-        uint32_t last = bit(n);
-        for (uint32_t S = below(i); S < last && S != 0; S = next_same_popcount(S)) {
-            if (!connected(&g, S)) continue;
-            C.connected_sets++;
-            double cardS = card_of(&g, S);
-            best_t b = {0, 0, 0, 0};
-            if (tree) {
-                /* Alg. 2: one join pair per edge of the tree G[S]; both
-                   orientations of each pair are costed. */
-                for (uint32_t T = S; T; T &= T - 1) {
-                    int v = lowest(T);
-                    for (uint32_t U = g.adj[v] & S & below(v); U; U &= U - 1) {
-                        int u = lowest(U);
-                        uint32_t L = grow(&g, bit(u), S & ~bit(v));
-                        uint32_t R = S & ~L;
-                        C.evaluated += 2;
-                        C.ccp_ordered += 2;
-                        consider(&g, &M, L, R, cardS, &b);
-                        consider(&g, &M, R, L, cardS, &b);
-                    }
-                }
-            } else {
-                /* Alg. 3: vertex-based enumeration inside each block, then
-                   grow the block pair to a pair of S. */
-                uint32_t blocks[32];
-                int nb = find_blocks(&g, S, blocks);
-                for (int k = 0; k < nb; k++) {
-                    uint32_t blk = blocks[k];
-                    for (uint32_t lb = (0u - blk) & blk; lb != 0; lb = (lb - blk) & blk) {
-                        if (lb == blk) continue; /* proper, non-empty subsets only */
-                        C.evaluated++;
-                        uint32_t rb = blk & ~lb;
-                        if (rb == 0 || lb == 0) continue;
-                        if (!connected(&g, lb)) continue;
-                        if (!connected(&g, rb)) continue;
-                        if ((rb & lb) != 0) continue;
-                        if (!adjacent(&g, lb, rb)) continue;
-                        C.ccp_ordered++;
-                        uint32_t L = grow(&g, lb, S & ~rb);
-                        uint32_t R = S & ~L;
-                        consider(&g, &M, L, R, cardS, &b);
-                    }
-                }
-            }
-            memo_store(&M, S, &b, cardS);
+        uint64_t ev = 0, cc = 0, cs = 0;
+        int64_t parts = (int64_t)1 << hi;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 1 ? nthreads : 1) reduction(+ : ev, cc, cs)
+        for (int64_t h = 0; h < parts; h++) {
+            ocount P = {0, 0, 0};
+            mpdp_part(&g, &M, tree, i, hi, (uint32_t)h, &P);
+            ev += P.evaluated; cc += P.ccp_ordered; cs += P.connected_sets;
         }
+        C.evaluated += ev; C.ccp_ordered += cc; C.connected_sets += cs;
     }
     counters[0] = C.evaluated; counters[1] = C.ccp_ordered; counters[2] = C.connected_sets;
     return 0;

@@ -52,6 +52,21 @@ def test_dp_algorithms_agree(cm):
 
 
 @pytest.mark.parametrize("cm", CMS)
+def test_threaded_levels_agree(cm):
+    """The level loop split over threads (sets of one size depend only on
+    smaller sets, Section 5) gives the same memo and counters as one thread,
+    also where the split puts every set of a level in its own part (n < 10)."""
+    qs = small_graphs()[:9] + [W.star(6, 0), W.cycle_chords(1, n=14, chords=5), W.clique(12, 2)]
+    for q in qs:
+        a = oracle.mpdp(q, cm)
+        for t in (2, 5):
+            b = oracle.mpdp(q, cm, threads=t)
+            same_memo(a, b)
+            assert (a.evaluated, a.ccp_ordered, a.connected_sets) == \
+                (b.evaluated, b.ccp_ordered, b.connected_sets), q.name
+
+
+@pytest.mark.parametrize("cm", CMS)
 def test_bruteforce_matches_dp(cm):
     nmax = 7 if cm == oracle.COST_COUT else 6
     qs = [W.random_connected(nmax, s, 0.3) for s in range(4)] + \
