@@ -15,7 +15,7 @@
  * join predicate, base cardinalities and edge selectivities.
  *
  * Shared definitions (the paper leaves estimation and cost formulas open,
- * Section 6.1; these are this library's):
+ * Section 7.1; these are this library's):
  *   card(S)  c = 1.0; for v in S ascending { c = c*card[v]; for u in S,
  *            u < v, (u,v) an edge, ascending: c = c*sel(u,v) };
  *            card(S) = (c < 1.0) ? 1.0 : c.  Evaluated in IEEE binary64,

@@ -6,7 +6,7 @@ oracle and the HIP path can consume the same arrays.
 
 Query information follows the paper's QI (Section 2, Alg. 1 input): the
 relations are vertices 0..n-1 of a join graph, each edge is an inner join
-predicate.  Workload shapes follow the synthetic workloads of Section 6.2.1
+predicate.  Workload shapes follow the synthetic workloads of Section 7.2.1
 (star, snowflake, clique) plus chains and cycles with extra chords.
 
 Distributions (shared by every generator):

@@ -3,7 +3,7 @@
 The oracle's counters are checked against mathematics that does not depend on
 the oracle: closed-form numbers of csg-cmp pairs and connected sets for
 chains, stars, cycles and cliques, and the evaluation ratios printed in the
-paper (Section 2.3 / Figure 4 and Section 6.2.1).
+paper (Section 2.3 / Figure 4 and Section 7.2.1).
 """
 import json
 import math
@@ -74,7 +74,7 @@ def test_tree_pairs_per_set():
 
 
 def test_star_dpsub_gap_printed_ratio():
-    """Figure 4 / Section 6.2.1: DPSUB's EvaluatedCounter is about 2805 times
+    """Figure 4 / Section 7.2.1: DPSUB's EvaluatedCounter is about 2805 times
     the CCP-Counter for a 25-relation star.  Alg. 1 evaluates every subset of
     every connected S, i.e. 2 * (3^(n-1) - 1) over the sets with |S| >= 2; the
     closed form is checked against the oracle's DPSUB counter first."""
@@ -89,7 +89,7 @@ def test_star_dpsub_gap_printed_ratio():
 
 
 def test_star_dpsize_gap_printed_ratio():
-    """Section 6.2.1: DPSIZE evaluates about 12024x more pairs than MPDP at 20
+    """Section 7.2.1: DPSIZE evaluates about 12024x more pairs than MPDP at 20
     relations.  DPSIZE pairs every connected set of size s with every one of
     size i-s; MPDP evaluates the ordered csg-cmp pairs."""
     g = GOLDEN["star_dpsize_gap"]
@@ -115,7 +115,7 @@ def test_star_dpsize_gap_printed_ratio():
 @pytest.mark.parametrize("maker", [lambda s: W.random_tree(10, s), lambda s: W.clique(8, s),
                                    lambda s: W.star(9, s)])
 def test_evaluated_equals_ccp_when_blocks_are_cliques(maker):
-    """Lemma in Section 3.2.3: if every block is a clique, EvaluatedCounter equals
+    """Lemma in Section 3.2.4 (Analysis): if every block is a clique, EvaluatedCounter equals
     CCP-Counter for Alg. 3 (trees: every block is one edge)."""
     q = maker(3)
     m = oracle.mpdp(q, force_general=True)
@@ -123,7 +123,7 @@ def test_evaluated_equals_ccp_when_blocks_are_cliques(maker):
 
 
 def test_block_enumeration_never_exceeds_dpsub():
-    """Section 3.2.3: per set, sum over blocks of 2^(b-1) <= 2^(|S|-1)."""
+    """Section 3.2.4 (Analysis): per set, sum over blocks of 2^(b-1) <= 2^(|S|-1)."""
     for seed in range(4):
         q = W.random_connected(10, seed, 0.25)
         m = oracle.mpdp(q)
