@@ -92,6 +92,10 @@ def main() -> int:
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--profile", choices=sorted(PROFILE_WORKLOADS),
+                    help="only run this workload a few times (a short program for rocprofv3) and print one line")
+    ap.add_argument("--profile-cost-model", type=int, default=0)
+    ap.add_argument("--profile-reps", type=int, default=2)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,6 +114,9 @@ def main() -> int:
         return 1
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile:
+        return profile_workload(mpdp, workloads, dev, args.profile, args.profile_cost_model, args.profile_reps,
+                                args.copy_probe_mib)
     n = args.n
     queries = [workloads.star(n, s) for s in range(args.queries)]
     ccp_per_query = (n - 1) * 2 ** (n - 2)
@@ -266,6 +273,56 @@ def main() -> int:
         }
 
     print(json.dumps(out), flush=True)
+    return 0
+
+
+# Short programs for the profiler: one family of kernels each.
+PROFILE_WORKLOADS = {
+    "star25": "star 25, seeds 0-1 (tree level kernels)",
+    "snowflake25": "snowflake 25, seeds 0-3 (tree level kernels, sparse levels)",
+    "cycle_p99": "cycle30+12-s15, the slowest C3a seed (filter, general and heavy kernels)",
+    "cycle_median": "cycle27+8-s8, a median C3a seed",
+    "clique18": "clique 18, seed 0 (general and heavy kernels)",
+    "batch": "the 4096-query mixed batch, one persistent launch",
+}
+
+
+def profile_workload(mpdp, workloads, dev, name, cm, reps, copy_mib):
+    import torch
+    if name == "batch":
+        qs = workloads.batch_mixed(4096, 0)
+        ws = mpdp.batch_workspace(qs)
+        for _ in range(reps):
+            r = mpdp.mpdp_optimize_batch(qs, cm, ws, flags=mpdp.MPDP_FLAG_TIMING)
+        info = {"queries": len(qs), "kernel_ms": r.stats["ms_kernel"], "ccp": r.stats["ccp_pairs"]}
+    else:
+        qs = {"star25": [workloads.star(25, s) for s in range(2)],
+              "snowflake25": [workloads.snowflake(25, s) for s in range(4)],
+              "cycle_p99": [workloads.cycle_chords(15)],
+              "cycle_median": [workloads.cycle_chords(8)],
+              "clique18": [workloads.clique(18, 0)]}[name]
+        ws = mpdp.workspace(max(q.n for q in qs), cm, dev)
+        info = {"queries": [q.name for q in qs], "ms": [], "ccp": 0, "evaluated": 0, "sets": 0}
+        for _ in range(reps):
+            for q in qs:
+                t = time.perf_counter()
+                r = mpdp.mpdp_optimize_ws(q, cm, ws)
+                info["ms"].append((time.perf_counter() - t) * 1e3)
+        for q in qs:
+            r = mpdp.mpdp_optimize_ws(q, cm, ws)
+            info["ccp"] += r.stats["ccp_pairs"]
+            info["evaluated"] += r.stats["evaluated_pairs"]
+            info["sets"] += r.stats["connected_sets"]
+    if copy_mib:
+        nb = copy_mib << 20
+        a = torch.ones(nb, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        info["copy_probe_bytes"] = nb
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": name, "cost_model": cm, "reps": reps, **info}), flush=True)
     return 0
 
 
