@@ -238,8 +238,10 @@ def goo(q, cm: int = COUT):
 
 # ------------------------------------------------------------------ IDP2
 
-def idp2(q, k: int, cm: int = COUT, initial=None):
-    """Section 4.1: IDP2 with GOO's plan as the initial tree (H5)."""
+def idp2(q, k: int, cm: int = COUT, initial=None, trace=None):
+    """Section 4.1: IDP2 with GOO's plan as the initial tree (H5).  With
+    `trace` (a list), the relation set of every re-planned subtree is
+    appended in the order IDP2 picks them."""
     G = Graph(q)
     cache = {}
     # tree over units: a unit is ("unit", relset, plan); a join ("join", A, B)
@@ -279,6 +281,8 @@ def idp2(q, k: int, cm: int = COUT, initial=None):
         S = 0
         for u in us:
             S |= u[1]
+        if trace is not None:
+            trace.append(S)
         new = ("unit", S, plan)
 
         def replace(t, p):

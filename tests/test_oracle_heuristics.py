@@ -160,3 +160,98 @@ def test_unit_query_of_single_relations_is_the_query():
     assert np.array_equal(uq.sel.view(np.uint64), q.sel[order].view(np.uint64))
     assert np.array_equal(uq.card.view(np.uint64), q.card.view(np.uint64))
     assert np.array_equal(uq.base_cost, 0.01 * q.card)
+
+
+def _leaf(v):
+    return ("leaf", v)
+
+
+def _join(a, b):
+    return ("join", a, b)
+
+
+IDP2_CHAIN = dict(edges=[[0, 1], [1, 2], [2, 3], [3, 4]], card=[4.0, 4.0, 4.0, 64.0, 64.0],
+                  sel=[0.5, 0.5, 0.25, 0.5])
+
+
+def idp2_chain():
+    return W.Query(5, np.array(IDP2_CHAIN["edges"], np.uint32), np.array(IDP2_CHAIN["card"]),
+                   np.array(IDP2_CHAIN["sel"]))
+
+
+def test_idp2_replans_the_costliest_subtree_by_hand():
+    """Section 4.1: IDP2 re-plans the subtree T' with 1 < |T'| <= k units of
+    maximal cost C(T').  Chain 0-1-2-3-4, cards (4, 4, 4, 64, 64), sels
+    (0.5, 0.5, 0.25, 0.5), C_out, k = 3, all values exact in binary:
+      card{0,1} = card{1,2} = 8, card{0,1,2} = 16, card{3,4} = 2048,
+      card{0,1,2,3} = 256, card of all = 8192.
+    From the tree ((0 1) 2) (3 4): the 2..3-unit subtrees cost (0 1) = 8,
+    ((0 1) 2) = 8 + 16 = 24, (3 4) = 2048.  The costliest is (3 4), which is
+    neither the first one met nor the cheapest.  Then ((0 1) 2) = 24 beats
+    (0 1) = 8; its exact plan ties 24 = 24 between (0 1) 2 and 0 (1 2), and
+    the smaller left set {0} wins: 0 (1 2).  Last the two units.  Result
+    (0 (1 2)) (3 4), cost 24 + 2048 + 8192 = 10264.
+    From GOO's tree (GOO: {0,1} = 8 ties {1,2} = 8 and the smaller lowest
+    relations win; then {0,1,2} = 16, {0,1,2,3} = 256, then 4): the
+    candidates are (0 1) = 8 and ((0 1) 2) = 24, so {0,1,2} is re-planned to
+    0 (1 2); then the root (3 units, 24 + 256 + 8192 = 8472) beats
+    (U 3) = 280; its exact plan over U = {0,1,2}, 3, 4 compares
+    U (3 4) = 24 + 2048 + 8192 = 10264 with (U 3) 4 = 24 + 256 + 8192 = 8472.
+    Picking the cheapest or the first subtree re-plans {0,1} first and keeps
+    (0 1) 2 instead."""
+    q = idp2_chain()
+    initial = _join(_join(_join(_leaf(0), _leaf(1)), _leaf(2)), _join(_leaf(3), _leaf(4)))
+    trace = []
+    p = H.idp2(q, 3, oracle.COST_COUT, initial=initial, trace=trace)
+    assert trace == [0b11000, 0b00111, 0b11111]
+    assert p == _join(_join(_leaf(0), _join(_leaf(1), _leaf(2))), _join(_leaf(3), _leaf(4)))
+    c, _ = H.report(q, p, oracle.COST_COUT)
+    assert c == 10264.0
+
+    assert H.goo(q) == _join(_join(_join(_join(_leaf(0), _leaf(1)), _leaf(2)), _leaf(3)), _leaf(4))
+    trace = []
+    p = H.idp2(q, 3, oracle.COST_COUT, trace=trace)
+    assert trace == [0b00111, 0b11111]
+    assert p == _join(_join(_join(_leaf(0), _join(_leaf(1), _leaf(2))), _leaf(3)), _leaf(4))
+    c, _ = H.report(q, p, oracle.COST_COUT)
+    assert c == 8472.0
+
+
+UNION_LADDER = dict(edges=[[0, 1], [1, 2], [2, 3], [0, 3], [3, 4], [4, 5]], card=[8.0] * 6,
+                    sel=[0.125, 0.5, 0.125, 0.25, 0.1875, 0.125])
+
+
+def union_ladder():
+    return W.Query(6, np.array(UNION_LADDER["edges"], np.uint32), np.array(UNION_LADDER["card"]),
+                   np.array(UNION_LADDER["sel"]))
+
+
+def test_uniondp_composite_edge_multiplies_its_selectivities_by_hand():
+    """Alg. 4 (composite nodes) with H3: two units joined by several base
+    edges get one edge whose selectivity is the product of theirs.
+    Relations 0..5, all cards 8, edges (0,1) 0.125, (1,2) 0.5, (2,3) 0.125,
+    (0,3) 0.25, (3,4) 0.1875, (4,5) 0.125; C_out, k = 3.
+    Partition: the weights of (0,1), (2,3), (4,5) are 8*8*0.125 = 8, the
+    others 32, 16, 12; the three pairs join first and every other union
+    would hold 4 > 3 units.  Units U0 = {0,1}, U1 = {2,3}, U2 = {4,5}, cards
+    8, base costs 8.  The unit query's edges: U0-U1 through (1,2) and (0,3),
+    selectivity 0.5 * 0.25 = 0.125; U1-U2 through (3,4), 0.1875.
+    Exact step: (U0 U1) U2 pays card(U0 u U1) = 8*8*0.125 = 8, U0 (U1 U2)
+    pays 8*8*0.1875 = 12: the first wins.  With only the first selectivity
+    (0.5 -> 32), only the second (0.25 -> 16), their sum or their minimum,
+    the other plan would win.  Re-costed over the base relations:
+    card{0,1,2,3} = 8, card of all = 12, cost 8 + 8 + 8 + 8 + 12 = 44."""
+    q = union_ladder()
+    G = H.Graph(q)
+    units = [(1 << v, _leaf(v)) for v in range(6)]
+    groups = H.partition(G, units, 3)
+    assert [sum(u[0] for u in g) for g in groups] == [0b000011, 0b001100, 0b110000]
+    uq, _ = H.unit_query(G, [(0b000011, _join(_leaf(0), _leaf(1))), (0b001100, _join(_leaf(2), _leaf(3))),
+                             (0b110000, _join(_leaf(4), _leaf(5)))], oracle.COST_COUT)
+    assert uq.edges.tolist() == [[0, 1], [1, 2]]
+    assert uq.sel.tolist() == [0.125, 0.1875]
+    assert uq.card.tolist() == [8.0, 8.0, 8.0] and uq.base_cost.tolist() == [8.0, 8.0, 8.0]
+    p = H.uniondp(q, 3, oracle.COST_COUT)
+    assert p == _join(_join(_join(_leaf(0), _leaf(1)), _join(_leaf(2), _leaf(3))), _join(_leaf(4), _leaf(5)))
+    c, _ = H.report(q, p, oracle.COST_COUT)
+    assert c == 44.0
