@@ -120,3 +120,25 @@ def test_large_fullsize_against_stored_oracle():
         r = mpdp.mpdp_optimize_large(q, g["cost_model"], methods[g["method"]], max(g["k"], 2))
         assert _hexbits(r.cost) == g["cost"], g
         assert _plan_hash(r.plan) == g["plan_sha256"], g
+
+
+def test_hand_worked_heuristic_cases():
+    """The library's IDP2 and UnionDP on the two cases worked by hand in
+    tests/test_oracle_heuristics.py: IDP2 from GOO's tree on the five-relation
+    chain (k = 3) re-plans {0,1,2} to 0 (1 2) and ends at ((0 (1 2)) 3) 4,
+    cost 8472; UnionDP on the six-relation ladder (k = 3) joins its three
+    pairs and, through the composite edge of selectivity 0.125, plans
+    ((0 1) (2 3)) (4 5), cost 44."""
+    from test_oracle_heuristics import _join, _leaf, idp2_chain, union_ladder
+    cm = mpdp.MPDP_COST_COUT
+    cases = [(idp2_chain(), mpdp.MPDP_LARGE_IDP2, 8472.0,
+              _join(_join(_join(_leaf(0), _join(_leaf(1), _leaf(2))), _leaf(3)), _leaf(4))),
+             (union_ladder(), mpdp.MPDP_LARGE_UNIONDP, 44.0,
+              _join(_join(_join(_leaf(0), _leaf(1)), _join(_leaf(2), _leaf(3))), _join(_leaf(4), _leaf(5))))]
+    for q, method, cost, plan in cases:
+        r = mpdp.mpdp_optimize_large(q, cm, method, 3)
+        assert r.cost == cost, (method, r.cost)
+        _, nodes = H.report(q, plan, cm)
+        for a, b in zip(r.plan, nodes):
+            assert (a["left"], a["right"], a["rel"], a["nrels"], a["op"]) == \
+                (b["left"], b["right"], b["rel"], b["nrels"], b["op"]), method
