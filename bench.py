@@ -30,8 +30,10 @@ configs    the paper-shaped single queries: star 12, snowflake 25 (both
            optimize time median / p99 over the seeds, ccp pairs per second
 ablations  the same optimizer with DPSUB's vertex-based candidates on the GPU,
            and the tree kernel without its LDS compaction (results unchanged)
-cpu_allcores  the library's multi-threaded CPU MPDP on the star (16 threads
-           at most), next to the single-thread oracle of cpu_baseline
+cpu_allcores  the library's multi-threaded CPU MPDP on the star, on one
+           GPU's share of the host's cores (16 threads at most; the host's
+           core count and CPU model are recorded), next to the single-thread
+           oracle of cpu_baseline
 """
 from __future__ import annotations
 
@@ -48,6 +50,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ccp pairs evaluated/sec + optimize time (ms) 25-rel star; learned vs plain cost ratio"
 HBM_PEAK_GBS = 8000.0
+CPU_SHARE_PER_GPU = 16   # host threads one GPU's jobs may use on a shared GPU host
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level_tree_star25.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2202_13511_amd", "csrc", f)
                for f in ("mpdp_kernels.hip", "mpdp_device.h", "mpdp_internal.h")]
@@ -244,14 +247,16 @@ def main() -> int:
 
     if not args.no_ablations:
         out["ablations"] = bench_ablations(mpdp, workloads, dev)
-        threads = min(16, os.cpu_count() or 1)
+        host = host_cpu()
+        threads = host["cpu_share"]
         q = queries[0]
         t = time.perf_counter()
         r = mpdp.mpdp_optimize_cpu(q, mpdp.MPDP_COST_COUT, threads)
         cdt = time.perf_counter() - t
         cpu_rate = r.stats["ccp_pairs"] / cdt
         out["cpu_allcores"] = {"value": cpu_rate, "unit": "ccp pairs/s", "threads": threads,
-                               "optimize_ms": cdt * 1e3, "query": q.name, "gpu_speedup": value / cpu_rate}
+                               "optimize_ms": cdt * 1e3, "query": q.name, "gpu_speedup": value / cpu_rate,
+                               **host}
 
     if not args.no_cpu_baseline:
         import oracle
@@ -268,12 +273,33 @@ def main() -> int:
             "sample": f"{q.name}: one query of the batch, C_out, oracle MPDP (plain C, one thread), "
                       f"{cdt:.1f} s",
             "optimize_ms": cdt * 1e3,
+            "cpu_model": host_cpu()["cpu_model"],
             "root_cost_bits_equal": bool(np.float64(gpu_root).view(np.uint64)
                                          == np.float64(m.root_cost).view(np.uint64)),
         }
 
     print(json.dumps(out), flush=True)
     return 0
+
+
+def host_cpu():
+    """The host's CPU model and core counts.  A GPU host shared by several
+    GPUs gives each one a share of its cores (CPU_SHARE_PER_GPU threads):
+    the all-cores baseline uses that share, or every core the process may
+    run on if fewer."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    visible = os.cpu_count() or 1
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else visible
+    return {"cpu_model": model, "host_cores": visible, "cores_allowed": allowed,
+            "cpu_share": max(1, min(allowed, CPU_SHARE_PER_GPU))}
 
 
 # Short programs for the profiler: one family of kernels each.

@@ -48,7 +48,9 @@ typedef enum {
     MPDP_ENOTCONNECTED = 2,  /* join graph disconnected: no cross-product-free plan */
     MPDP_ETOOLARGE = 3,      /* n > 32: beyond the bitmap width of the exact DP    */
     MPDP_ENOMEM = 4,         /* workspace too small, or device allocation failed   */
-    MPDP_EDEVICE = 5         /* a HIP runtime error                                */
+    MPDP_EDEVICE = 5,        /* a HIP runtime error                                */
+    MPDP_ETIMEOUT = 6        /* budgeted heuristics: the time budget ran out; the
+                                outputs hold the complete plan found so far       */
 } mpdp_status;
 
 typedef enum { MPDP_COST_COUT = 0, MPDP_COST_PGLIKE = 1 } mpdp_cost_model;
@@ -406,6 +408,28 @@ mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
                                 mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
                                 const void *d_scorer, void *hip_stream, mpdp_large_node *plan_out,
                                 double *cost_out, mpdp_large_stats *stats_out);
+
+/*
+ * mpdp_optimize_large with a wall-clock budget (Section 4.1: IDP2 can stop
+ * whenever a budget is exhausted), budget_ms > 0 counted from the call's
+ * start (0: none; negative or non-finite: MPDP_EINVAL).  The budget is
+ * checked before every exact sub-problem and every scored pass of the
+ * learned partition; a sub-problem already started runs to its end.  When
+ * it has run out, the call returns MPDP_ETIMEOUT with plan_out, cost_out and
+ * stats_out written:
+ *   IDP2     the GOO start with the subtrees re-planned so far (every
+ *            re-planning only lowers the cost, so this is never worse than
+ *            GOO alone);
+ *   UnionDP  (plain or learned) the units of the current round, each with
+ *            its exact plan, joined by GOO (smallest union card first);
+ *   GOO      ignores the budget.
+ */
+mpdp_status mpdp_optimize_large_budget(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                       const double *cardinalities, const double *selectivities,
+                                       mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
+                                       const void *d_scorer, double budget_ms, void *hip_stream,
+                                       mpdp_large_node *plan_out, double *cost_out,
+                                       mpdp_large_stats *stats_out);
 
 /*
  * Training examples for the scorer from a query of n <= 32 relations whose

@@ -61,15 +61,19 @@ struct Query {
     double sel_full[32 * 32];  // host only: sel[u * 32 + v], symmetric, 0 without an edge
 };
 
-// C(a, b) for a, b <= 32 at [a * 33 + b], computed once.
+// C(a, b) for a, b <= 32 at [a * 33 + b], computed once (static storage,
+// no heap).
+struct BinomTable {
+    uint32_t v[33 * 33];
+};
 const uint32_t *binom_table() {
-    static const std::vector<uint32_t> t = [] {
-        std::vector<uint32_t> v(33 * 33);
+    static const BinomTable t = [] {
+        BinomTable b{};
         for (uint32_t a = 0; a <= 32; ++a)
-            for (uint32_t b = 0; b <= 32; ++b) v[a * 33 + b] = (uint32_t)binom64(a, b);
-        return v;
+            for (uint32_t c = 0; c <= 32; ++c) b.v[a * 33 + c] = (uint32_t)binom64(a, c);
+        return b;
     }();
-    return t.data();
+    return t.v;
 }
 
 // Validation runs entirely on the host, before any HIP call.  base_costs
@@ -972,9 +976,10 @@ const char *mpdp_status_str(mpdp_status s) {
         case MPDP_OK: return "ok";
         case MPDP_EINVAL: return "invalid argument";
         case MPDP_ENOTCONNECTED: return "join graph is not connected";
-        case MPDP_ETOOLARGE: return "more than 32 relations";
+        case MPDP_ETOOLARGE: return "too many relations for this entry point";
         case MPDP_ENOMEM: return "workspace too small or device allocation failed";
         case MPDP_EDEVICE: return "HIP runtime error";
+        case MPDP_ETIMEOUT: return "time budget exhausted (the plan found so far was returned)";
     }
     return "unknown status";
 }

@@ -222,6 +222,9 @@ struct ExactCtx {
     size_t ws_bytes = 0;
     std::vector<int> where;  // relation -> local unit index, -1 outside
     mpdp_large_stats st{};
+    // time budget: wall clock of the call's start and its limit (0: none)
+    double t0 = 0.0, budget_ms = 0.0;
+    bool over_budget() const { return budget_ms > 0.0 && now_ms() - t0 >= budget_ms; }
     // learned union order: scorer parameters (device) and scratch
     const void *scorer = nullptr;
     void *sc_buf = nullptr;
@@ -364,7 +367,11 @@ mpdp_status exact_groups(ExactCtx &X, const std::vector<std::vector<const Unit *
 
 // ---------------------------------------------------------------- GOO
 
-int goo(const Graph &G, Pool &P) {
+// GOO from a list of starting trees (relation sets with their plans, in
+// order of their lowest relation): join the two adjacent trees whose union
+// has the smallest card (ties: the smaller tree indices) until one is left.
+int goo_from(const Graph &G, Pool &P, const std::vector<Bits> &rels, const std::vector<int> &plans,
+             const std::vector<int> &where) {
     struct Tree {
         Bits rels;
         int plan;
@@ -372,20 +379,24 @@ int goo(const Graph &G, Pool &P) {
         std::set<uint32_t> nbrs;
         bool alive;
     };
-    std::vector<Tree> T(G.n);
+    const uint32_t nt = (uint32_t)rels.size();
+    std::vector<Tree> T(nt);
     uint32_t version = 0;
-    for (uint32_t v = 0; v < G.n; ++v) {
-        T[v] = Tree{G.single(v), P.leaf(v), version++, {}, true};
-        for (uint32_t u : G.adj[v]) T[v].nbrs.insert(u);
+    for (uint32_t t = 0; t < nt; ++t) T[t] = Tree{rels[t], plans[t], version++, {}, true};
+    std::set<std::pair<uint32_t, uint32_t>> tedges;
+    for (size_t e = 0; e < G.eu.size(); ++e) {
+        const uint32_t a = (uint32_t)where[G.eu[e]], b = (uint32_t)where[G.ev[e]];
+        if (a == b) continue;
+        T[a].nbrs.insert(b);
+        T[b].nbrs.insert(a);
+        tedges.insert({std::min(a, b), std::max(a, b)});
     }
     using Cand = std::tuple<double, uint32_t, uint32_t, uint32_t, uint32_t>;  // card, i, j, ver i, ver j
     std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> heap;
-    for (size_t e = 0; e < G.eu.size(); ++e) {
-        const uint32_t i = std::min(G.eu[e], G.ev[e]), j = std::max(G.eu[e], G.ev[e]);
+    for (const auto &[i, j] : tedges)
         heap.push(Cand{G.card_of(T[i].rels | T[j].rels), i, j, T[i].version, T[j].version});
-    }
-    uint32_t left = G.n;
-    int root = G.n == 1 ? T[0].plan : -1;
+    uint32_t left = nt;
+    int root = nt == 1 ? T[0].plan : -1;
     while (left > 1 && !heap.empty()) {
         const auto [c, i, j, vi, vj] = heap.top();
         heap.pop();
@@ -412,6 +423,30 @@ int goo(const Graph &G, Pool &P) {
         root = A.plan;
     }
     return left == 1 ? root : -1;
+}
+
+int goo(const Graph &G, Pool &P) {
+    std::vector<Bits> rels;
+    std::vector<int> plans, where(G.n);
+    for (uint32_t v = 0; v < G.n; ++v) {
+        rels.push_back(G.single(v));
+        plans.push_back(P.leaf(v));
+        where[v] = (int)v;
+    }
+    return goo_from(G, P, rels, plans, where);
+}
+
+// GOO over the current units of a budgeted run that has run out of time.
+int goo_units(const Graph &G, Pool &P, std::vector<Unit> units) {
+    std::sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.low < b.low; });
+    std::vector<Bits> rels;
+    std::vector<int> plans, where(G.n, -1);
+    for (size_t i = 0; i < units.size(); ++i) {
+        rels.push_back(units[i].rels);
+        plans.push_back(units[i].plan);
+        units[i].rels.each([&](uint32_t v) { where[v] = (int)i; });
+    }
+    return goo_from(G, P, rels, plans, where);
 }
 
 // ---------------------------------------------------------------- IDP2
@@ -449,6 +484,16 @@ mpdp_status idp2(ExactCtx &X, int start, uint32_t k, int &result) {
     };
     const int root = conv(start);
     while (T[root].unit < 0) {
+        if (X.over_budget()) {
+            // anytime: the start tree with the subtrees re-planned so far
+            std::function<int(int)> plan_of = [&](int x) -> int {
+                if (T[x].unit >= 0) return units[T[x].unit].plan;
+                const int a = plan_of(T[x].l);
+                return P.join(a, plan_of(T[x].r));
+            };
+            result = plan_of(root);
+            return MPDP_ETIMEOUT;
+        }
         X.st.rounds += 1;
         // post-order: units below, relation set, cost (re-costing from the children)
         int best = -1;
@@ -654,6 +699,7 @@ mpdp_status learned_partition(ExactCtx &X, const std::vector<Unit> &units, const
     std::vector<uint16_t> feat;
     std::vector<float> score;
     for (;;) {
+        if (X.over_budget()) return MPDP_ETIMEOUT;
         std::vector<std::pair<uint32_t, uint32_t>> pairs;
         for (const auto &e : ue) {
             const uint32_t a = owner[e.first], b = owner[e.second];
@@ -728,7 +774,13 @@ mpdp_status uniondp(ExactCtx &X, uint32_t k, int &result) {
     std::vector<Unit> units;
     for (uint32_t v = 0; v < G.n; ++v) units.push_back(Unit{G.single(v), X.P->leaf(v), v});
     std::vector<int> where(G.n, -1);
+    // out of time: the current units joined greedily
+    auto finish = [&]() {
+        result = goo_units(G, *X.P, units);
+        return result < 0 ? MPDP_ENOTCONNECTED : MPDP_ETIMEOUT;
+    };
     while (units.size() > k) {
+        if (X.over_budget()) return finish();
         X.st.rounds += 1;
         std::sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.low < b.low; });
         for (size_t i = 0; i < units.size(); ++i) units[i].rels.each([&](uint32_t v) { where[v] = (int)i; });
@@ -736,6 +788,7 @@ mpdp_status uniondp(ExactCtx &X, uint32_t k, int &result) {
         bool have = false;
         if (X.scorer || X.teacher) {
             mpdp_status ls = learned_partition(X, units, where, k, gl, have);
+            if (ls == MPDP_ETIMEOUT) return finish();
             if (ls != MPDP_OK) return ls;
         }
         if (!have) {  // the paper's partition phase
@@ -796,6 +849,7 @@ mpdp_status uniondp(ExactCtx &X, uint32_t k, int &result) {
         }
         units = std::move(next);
     }
+    if (X.over_budget()) return finish();
     std::vector<const Unit *> all;
     for (const Unit &u : units) all.push_back(&u);
     std::vector<int> plans;
@@ -879,13 +933,15 @@ void write_plan(Pool &P, int root, mpdp_large_node *out, uint32_t n) {
 
 }  // namespace
 
-extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
-                                           const double *cardinalities, const double *selectivities,
-                                           mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
-                                           const void *d_scorer, void *hip_stream, mpdp_large_node *plan_out,
-                                           double *cost_out, mpdp_large_stats *stats_out) {
+extern "C" mpdp_status mpdp_optimize_large_budget(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                                  const double *cardinalities, const double *selectivities,
+                                                  mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
+                                                  const void *d_scorer, double budget_ms, void *hip_stream,
+                                                  mpdp_large_node *plan_out, double *cost_out,
+                                                  mpdp_large_stats *stats_out) {
     const double t0 = now_ms();
     if (!plan_out || !cost_out) return MPDP_EINVAL;
+    if (!std::isfinite(budget_ms) || budget_ms < 0.0) return MPDP_EINVAL;
     if (method != MPDP_LARGE_GOO && method != MPDP_LARGE_IDP2 && method != MPDP_LARGE_UNIONDP &&
         method != MPDP_LARGE_UNIONDP_LEARNED)
         return MPDP_EINVAL;
@@ -903,6 +959,8 @@ extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_ed
     X.P = &P;
     X.s = static_cast<hipStream_t>(hip_stream);
     X.where.assign(n, -1);
+    X.t0 = t0;
+    X.budget_ms = method == MPDP_LARGE_GOO ? 0.0 : budget_ms;
     if (method == MPDP_LARGE_UNIONDP_LEARNED) X.scorer = d_scorer;
     int root = -1;
     if (method == MPDP_LARGE_UNIONDP || method == MPDP_LARGE_UNIONDP_LEARNED) {
@@ -915,7 +973,7 @@ extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_ed
             st = idp2(X, start, k, root);
         }
     }
-    if (st != MPDP_OK) return st;
+    if (st != MPDP_OK && st != MPDP_ETIMEOUT) return st;
     P.recost(root);
     write_plan(P, root, plan_out, n);
     *cost_out = P.nodes[root].cost;
@@ -923,7 +981,16 @@ extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_ed
         X.st.ms_total = now_ms() - t0;
         *stats_out = X.st;
     }
-    return MPDP_OK;
+    return st;
+}
+
+extern "C" mpdp_status mpdp_optimize_large(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                           const double *cardinalities, const double *selectivities,
+                                           mpdp_cost_model cost_model, mpdp_large_method method, uint32_t k,
+                                           const void *d_scorer, void *hip_stream, mpdp_large_node *plan_out,
+                                           double *cost_out, mpdp_large_stats *stats_out) {
+    return mpdp_optimize_large_budget(n, m, edges, cardinalities, selectivities, cost_model, method, k, d_scorer,
+                                      0.0, hip_stream, plan_out, cost_out, stats_out);
 }
 
 extern "C" mpdp_status mpdp_large_examples(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *cardinalities,

@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpdp.so")
 
-MPDP_OK, MPDP_EINVAL, MPDP_ENOTCONNECTED, MPDP_ETOOLARGE, MPDP_ENOMEM, MPDP_EDEVICE = range(6)
+MPDP_OK, MPDP_EINVAL, MPDP_ENOTCONNECTED, MPDP_ETOOLARGE, MPDP_ENOMEM, MPDP_EDEVICE, MPDP_ETIMEOUT = range(7)
 MPDP_COST_COUT, MPDP_COST_PGLIKE = 0, 1
 MPDP_OP_SCAN, MPDP_OP_HASH, MPDP_OP_NESTLOOP, MPDP_OP_JOIN = 0, 1, 2, 3
 MPDP_FLAG_TIMING = 1
@@ -29,7 +29,7 @@ EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp
             "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_optimize_cpu", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
             "mpdp_optimize_batch_sched", "mpdp_batch_autotune", "mpdp_batch_graph_create", "mpdp_batch_graph_run",
             "mpdp_batch_graph_destroy",
-            "mpdp_optimize_large", "mpdp_large_examples", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
+            "mpdp_optimize_large", "mpdp_optimize_large_budget", "mpdp_large_examples", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
             "mpdp_scorer_load", "mpdp_scorer_forward", "mpdp_scorer_grad", "mpdp_scorer_train_step"]
 SCORER_IN, SCORER_HIDDEN = 32, 256
 MPDP_LARGE_GOO, MPDP_LARGE_IDP2, MPDP_LARGE_UNIONDP, MPDP_LARGE_UNIONDP_LEARNED = 0, 1, 2, 3
@@ -132,6 +132,10 @@ def load(path: str = LIB_PATH):
                                                ctypes.POINTER(ctypes.c_float), u32, ctypes.POINTER(ctypes.c_uint32)]
     L.mpdp_large_examples.restype = ctypes.c_int
     L.mpdp_optimize_large.restype = ctypes.c_int
+    L.mpdp_optimize_large_budget.argtypes = common + [ctypes.c_int, u32, vp, ctypes.c_double, vp,
+                                                      ctypes.POINTER(mpdp_large_node), f64p,
+                                                      ctypes.POINTER(mpdp_large_stats)]
+    L.mpdp_optimize_large_budget.restype = ctypes.c_int
     L.mpdp_scorer_param_bytes.argtypes = []
     L.mpdp_scorer_param_bytes.restype = sz
     L.mpdp_scorer_work_bytes.argtypes = [u32]
@@ -305,10 +309,13 @@ class LargeResult:
     stats: dict
 
 
-def mpdp_optimize_large(query, cost_model: int, method: int, k: int, scorer=None, stream=None) -> LargeResult:
+def mpdp_optimize_large(query, cost_model: int, method: int, k: int, scorer=None, stream=None,
+                        budget_ms: float | None = None) -> LargeResult:
     """Large-query heuristics (GOO, IDP2, UnionDP, learned UnionDP) with the
     exact DP on the GPU as the inner step; the library owns its device
-    workspace.  scorer: a device parameter block (scorer_params())."""
+    workspace.  scorer: a device parameter block (scorer_params()).
+    budget_ms: a wall-clock budget (mpdp_optimize_large_budget); a run that
+    exhausts it returns the plan found so far with stats["timed_out"] set."""
     n, edges, card, sel = _args(query)
     keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
     plan = (mpdp_large_node * max(2 * n - 1, 1))()
@@ -316,13 +323,20 @@ def mpdp_optimize_large(query, cost_model: int, method: int, k: int, scorer=None
     stats = mpdp_large_stats()
     sp_handle = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
     sc = None if scorer is None else ctypes.c_void_p(scorer.data_ptr())
-    st = load().mpdp_optimize_large(int(n), m, ep, cp, sp, int(cost_model), int(method), int(k), sc, sp_handle,
-                                    plan, ctypes.byref(cost), ctypes.byref(stats))
-    if st != MPDP_OK:
+    if budget_ms is None:
+        st = load().mpdp_optimize_large(int(n), m, ep, cp, sp, int(cost_model), int(method), int(k), sc,
+                                        sp_handle, plan, ctypes.byref(cost), ctypes.byref(stats))
+    else:
+        st = load().mpdp_optimize_large_budget(int(n), m, ep, cp, sp, int(cost_model), int(method), int(k), sc,
+                                               float(budget_ms), sp_handle, plan, ctypes.byref(cost),
+                                               ctypes.byref(stats))
+    if st not in (MPDP_OK, MPDP_ETIMEOUT):
         raise MpdpError(st, mpdp_status_str(st))
     nodes = [dict(left=p.left, right=p.right, rel=p.rel, nrels=p.nrels, op=p.op, cost=p.cost, card=p.card)
              for p in plan[: 2 * n - 1]]
-    return LargeResult(cost.value, nodes, {f: getattr(stats, f) for f, _ in mpdp_large_stats._fields_})
+    info = {f: getattr(stats, f) for f, _ in mpdp_large_stats._fields_}
+    info["timed_out"] = st == MPDP_ETIMEOUT
+    return LargeResult(cost.value, nodes, info)
 
 
 def mpdp_large_examples(query, cost_model: int, k: int, plan_sets, scorer=None, stream=None):

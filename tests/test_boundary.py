@@ -32,8 +32,8 @@ def test_library_exports_every_declared_function():
 
 
 def test_status_strings():
-    for s in range(6):
-        assert mpdp.mpdp_status_str(s)
+    for s in range(7):
+        assert mpdp.mpdp_status_str(s) != "unknown status"
     assert mpdp.mpdp_status_str(99) == "unknown status"
 
 

@@ -142,3 +142,24 @@ def test_hand_worked_heuristic_cases():
         for a, b in zip(r.plan, nodes):
             assert (a["left"], a["right"], a["rel"], a["nrels"], a["op"]) == \
                 (b["left"], b["right"], b["rel"], b["nrels"], b["op"]), method
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_budget_partial_and_generous(cm):
+    """A budget that never runs out gives the unbudgeted plan bit for bit; one
+    that runs out part way returns MPDP_ETIMEOUT with a complete plan that,
+    for IDP2, costs no more than GOO's start (Section 4.1: stop whenever a
+    budget is exhausted)."""
+    q = W.large_snowflake(300, 1)
+    goo_cost = mpdp.mpdp_optimize_large(q, cm, mpdp.MPDP_LARGE_GOO, 2).cost
+    for method in (mpdp.MPDP_LARGE_IDP2, mpdp.MPDP_LARGE_UNIONDP):
+        print(q.name, cm, method, flush=True)
+        full = mpdp.mpdp_optimize_large(q, cm, method, 15)
+        r = mpdp.mpdp_optimize_large(q, cm, method, 15, budget_ms=1e6)
+        assert not r.stats["timed_out"] and bits(r.cost) == bits(full.cost)
+        assert r.plan == full.plan
+        r = mpdp.mpdp_optimize_large(q, cm, method, 15, budget_ms=max(0.3 * full.stats["ms_total"], 0.05))
+        assert r.stats["timed_out"], (q.name, method)
+        assert r.plan[-1]["nrels"] == q.n and len(r.plan) == 2 * q.n - 1
+        if method == mpdp.MPDP_LARGE_IDP2:
+            assert r.cost <= goo_cost

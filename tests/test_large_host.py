@@ -48,3 +48,31 @@ def test_large_validation():
     one = W.Query(1, np.zeros((0, 2), np.uint32), np.array([50.0]), np.zeros(0))
     r = mpdp.mpdp_optimize_large(one, mpdp.MPDP_COST_PGLIKE, mpdp.MPDP_LARGE_GOO, 2)
     assert r.cost == 0.5 and r.plan[0]["rel"] == 0
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_budget_exhausted_before_any_exact_step(cm):
+    """Section 4.1's budget: a budget that is over before the first exact
+    sub-problem leaves IDP2 with its GOO start, and UnionDP joins its units
+    (still single relations) by GOO; both report MPDP_ETIMEOUT with the plan,
+    and no HIP call is made."""
+    for q in [W.large_snowflake(100, 1), W.snowflake(14, 3), W.cycle_chords(2, n=12, chords=3)]:
+        c, nodes = H.report(q, H.goo(q, cm), cm)
+        for method in (mpdp.MPDP_LARGE_IDP2, mpdp.MPDP_LARGE_UNIONDP):
+            r = mpdp.mpdp_optimize_large(q, cm, method, 10, budget_ms=1e-9)
+            assert r.stats["timed_out"], q.name
+            assert bits(r.cost) == bits(c), (q.name, method)
+            for a, b in zip(nodes, r.plan):
+                for f in ("left", "right", "rel", "nrels", "op"):
+                    assert a[f] == b[f], (q.name, method, f)
+        # GOO ignores the budget
+        r = mpdp.mpdp_optimize_large(q, cm, mpdp.MPDP_LARGE_GOO, 2, budget_ms=1e-9)
+        assert not r.stats["timed_out"] and bits(r.cost) == bits(c)
+
+
+def test_budget_validation():
+    q = W.chain(8, 0)
+    for b in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(mpdp.MpdpError) as e:
+            mpdp.mpdp_optimize_large(q, 0, mpdp.MPDP_LARGE_IDP2, 5, budget_ms=b)
+        assert e.value.status == mpdp.MPDP_EINVAL
