@@ -4,9 +4,11 @@ tests/golden/oracle_fullsize.json is written by
 tests/golden/make_oracle_golden.py from the CPU oracle alone.  Every query
 is optimized through the C-ABI in the launch configuration the benchmark
 uses; the root cost (bit pattern), every join node of the plan, the counters
-and 32 sampled memo entries must match exactly.  Cyclic queries beyond the
-oracle's budget carry 16 sets solved by the oracle on their induced
-sub-queries instead, and their plan must re-cost exactly to the root cost.
+and 32 sampled memo entries must match exactly.  The cyclic queries of 27 or
+more relations also carry 16 connected sets (4 of them of 20-24 relations)
+solved by the oracle on their induced sub-queries; the whole query's memo
+entry of each must equal the sub-query's root, and the plan must re-cost
+exactly to the root cost.
 """
 import json
 import os
@@ -30,7 +32,7 @@ def make_query(g):
         return W.snowflake(g["n"], g["seed"])
     if g["kind"] == "clique":
         return W.clique(g["n"], g["seed"])
-    if g["kind"] == "cycle_chords":
+    if g["kind"] in ("cycle_chords", "cycle_sub"):
         return W.cycle_chords(g["seed"])
     raise ValueError(g["kind"])
 
@@ -63,38 +65,45 @@ KINDS = [("star", 12), ("star", 25), ("snowflake", 25), ("clique", 18), ("cycle_
 @pytest.mark.parametrize("kind,n", KINDS, ids=[f"{k}{n or ''}" for k, n in KINDS])
 def test_fullsize_parity(kind, n):
     import torch
-    qs = [g for g in GOLD if g["kind"] == kind and (n is None or g["n"] == n)]
-    if not qs:
+    kinds = ("cycle_chords", "cycle_sub") if kind == "cycle_chords" else (kind,)
+    # the stored checks of one query (whole result and / or sub-queries), by query
+    byq = {}
+    for g in GOLD:
+        if g["kind"] in kinds and (n is None or g["n"] == n):
+            byq.setdefault((g["seed"], g["cost_model"]), []).append(g)
+    if not byq:
         pytest.skip("no stored oracle results for this workload")
     wss = {}
-    for g in qs:
-        q = make_query(g)
-        assert q.n == g["n"] and q.m == g["m"], g["name"]
-        key = (q.n, g["cost_model"])
+    for (seed, cm), gs in byq.items():
+        q = make_query(gs[0])
+        for g in gs:
+            assert q.n == g["n"] and q.m == g["m"], g["name"]
+        key = (q.n, cm)
         if key not in wss:
             wss.clear()
             torch.cuda.empty_cache()
-            wss[key] = mpdp.workspace(q.n, g["cost_model"], "cuda")
+            wss[key] = mpdp.workspace(q.n, cm, "cuda")
         ws = wss[key]
-        print(f"{g['name']} cm={g['cost_model']}", flush=True)
-        res = mpdp.mpdp_optimize_ws(q, g["cost_model"], ws)
-        if g.get("sampled_only"):
-            # beyond the oracle's budget for the whole query: the plan must be
-            # a tree of csg-cmp pairs whose cost recomputes to the root cost
-            import oracle
-            assert oracle.recost_plan(q, res.plan, g["cost_model"]) == res.cost, g["name"]
-        else:
-            assert f"{int(np.float64(res.cost).view(np.uint64)):016x}" == g["root_cost"], g["name"]
-            joins = [[nd["relset"], res.plan[nd["left"]]["relset"], nd["op"]] for nd in res.plan[q.n:]]
-            assert joins == g["joins"], g["name"]
-            st = res.stats
-            assert st["connected_sets"] == g["connected_sets"], g["name"]
-            assert st["ccp_pairs"] == g["ccp_pairs"], g["name"]
-            assert st["evaluated_pairs"] == g["evaluated_pairs"], g["name"]
-        sets = [s[0] for s in g["samples"]]
-        cost, card, left, op = sampled_entries(ws, q.n, sets)
-        for i, (S, c, k, L, o) in enumerate(g["samples"]):
-            assert f"{int(cost[i]):016x}" == c and f"{int(card[i]):016x}" == k, (g["name"], S)
-            assert int(left[i]) == L and int(op[i]) == o, (g["name"], S)
+        print(f"{q.name} cm={cm} checks={[g['kind'] for g in gs]}", flush=True)
+        res = mpdp.mpdp_optimize_ws(q, cm, ws)
+        for g in gs:
+            if g.get("sampled_only"):
+                # the plan must be a tree of csg-cmp pairs whose cost
+                # recomputes to the root cost
+                import oracle
+                assert oracle.recost_plan(q, res.plan, cm) == res.cost, g["name"]
+            else:
+                assert f"{int(np.float64(res.cost).view(np.uint64)):016x}" == g["root_cost"], g["name"]
+                joins = [[nd["relset"], res.plan[nd["left"]]["relset"], nd["op"]] for nd in res.plan[q.n:]]
+                assert joins == g["joins"], g["name"]
+                st = res.stats
+                assert st["connected_sets"] == g["connected_sets"], g["name"]
+                assert st["ccp_pairs"] == g["ccp_pairs"], g["name"]
+                assert st["evaluated_pairs"] == g["evaluated_pairs"], g["name"]
+            sets = [s[0] for s in g["samples"]]
+            cost, card, left, op = sampled_entries(ws, q.n, sets)
+            for i, (S, c, k, L, o) in enumerate(g["samples"]):
+                assert f"{int(cost[i]):016x}" == c and f"{int(card[i]):016x}" == k, (g["name"], g["kind"], S)
+                assert int(left[i]) == L and int(op[i]) == o, (g["name"], g["kind"], S)
     wss.clear()
     torch.cuda.empty_cache()
