@@ -159,6 +159,33 @@ mpdp_status mpdp_optimize_ws(uint32_t n, uint32_t m, const mpdp_edge *edges,
                              void *hip_stream, uint32_t flags, mpdp_plan_node *plan_out,
                              double *cost_out, mpdp_stats *stats_out);
 
+/* Largest query mpdp_optimize_noalloc takes. */
+#define MPDP_NOALLOC_MAX_REL 20u
+
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mpdp_optimize_ws with the
+ * workspace replaced by a fixed device array inside the library.
+ *   n             at most MPDP_NOALLOC_MAX_REL; MPDP_ETOOLARGE beyond
+ *   hip_stream    hipStream_t to enqueue on (NULL: the null stream)
+ *   flags         0 or the ablation flags; MPDP_FLAG_TIMING is MPDP_EINVAL
+ *   other arguments, outputs and validation as in mpdp_optimize_ws
+ * The call allocates nothing, on the host or the device: the array
+ * (mpdp_noalloc_scratch_bytes() bytes, 24 MiB) exists on every device the
+ * library runs on and is held until the process ends; its device address is
+ * looked up on the first call on each device.  The query information goes up
+ * and the plan comes back through pageable copies from the caller's thread.
+ * Every call on one device uses that device's one array, so calls that
+ * overlap on one device (from several threads or streams) race and must be
+ * serialised by the caller; each call rewrites everything it reads, so no
+ * state carries over from the previous call.  The call waits for its stream.
+ */
+size_t mpdp_noalloc_scratch_bytes(void);
+mpdp_status mpdp_optimize_noalloc(uint32_t n, uint32_t m, const mpdp_edge *edges,
+                                  const double *cardinalities, const double *selectivities,
+                                  mpdp_cost_model cost_model, void *hip_stream, uint32_t flags,
+                                  mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out);
+
 /*
  * As mpdp_optimize_ws for a query whose relations stand for intermediate
  * results that are already planned (the exact step of IDP2 and UnionDP,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpdp.so")
-SOURCES = ["mpdp_kernels.hip", "mpdp_batch.hip", "mpdp_scorer.hip", "mpdp_host.cpp", "mpdp_large.cpp", "mpdp_cpu.cpp"]
+SOURCES = ["mpdp_kernels.hip", "mpdp_batch.hip", "mpdp_scorer.hip", "mpdp_noalloc.hip", "mpdp_host.cpp", "mpdp_large.cpp", "mpdp_cpu.cpp"]
 
 
 def hipcc() -> str:

@@ -216,6 +216,10 @@ char *pinned_staging(size_t bytes) {
     return buf;
 }
 
+// Bytes of counters, plan and root cost read back per call, as far as the
+// no-allocation path keeps them on the stack (n <= 32 needs under 3 KB).
+constexpr size_t kNoAllocDownBytes = 4096;
+
 struct EventPool {
     std::vector<hipEvent_t> ev;
     ~EventPool() {
@@ -231,9 +235,14 @@ struct EventPool {
     }
 };
 
+// One exact optimization in the workspace d_ws on stream s.  With
+// no_alloc, nothing is allocated on the host or the device: the query
+// information goes up and the plan comes back through pageable memory (the
+// calling thread's stack), and MPDP_FLAG_TIMING is refused (its events
+// would be created here).
 mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint32_t flags,
                 mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out, double t0,
-                bool force_general) {
+                bool force_general, bool no_alloc = false) {
     const uint32_t n = q.n;
     const Layout L = make_layout(n);
     if (ws_bytes < L.total) return MPDP_ENOMEM;
@@ -249,6 +258,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     double *droot = reinterpret_cast<double *>(base + L.root);
 
     const bool timing = (flags & MPDP_FLAG_TIMING) != 0;
+    if (timing && no_alloc) return MPDP_EINVAL;
     EventPool ev;
     if (timing) HIPCHK(ev.make(4 * (size_t)n));
 
@@ -258,7 +268,9 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     // (plain DMA, no runtime-side staging copy); the call waits for its
     // stream before returning, so the buffer is free again by the next call
     const size_t down_bytes = L.root + sizeof(double) - L.counters;
-    char *pin = pinned_staging(sizeof(DevGraph) > down_bytes ? sizeof(DevGraph) : down_bytes);
+    alignas(16) char down_stack[kNoAllocDownBytes];
+    if (no_alloc && down_bytes > sizeof(down_stack)) return MPDP_ETOOLARGE;
+    char *pin = no_alloc ? nullptr : pinned_staging(sizeof(DevGraph) > down_bytes ? sizeof(DevGraph) : down_bytes);
     if (pin) {
         std::memcpy(pin, &q.g, sizeof(DevGraph));
         HIPCHK(hipMemcpyAsync(dg, pin, sizeof(DevGraph), hipMemcpyHostToDevice, s));
@@ -285,8 +297,8 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     }
     HIPCHK(mpdp::launch_extract(dg, n, memo, dplan, droot, cnt, s));
     // counters, plan and root cost are adjacent in the workspace: one copy back
-    std::vector<char> down_pageable(pin ? 0 : down_bytes);
-    char *down = pin ? pin : down_pageable.data();
+    std::vector<char> down_pageable((pin || no_alloc) ? 0 : down_bytes);
+    char *down = pin ? pin : (no_alloc ? down_stack : down_pageable.data());
     HIPCHK(hipMemcpyAsync(down, cnt, down_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     Counters hc;
@@ -839,6 +851,35 @@ mpdp_status optimize_units(uint32_t n, uint32_t m, const mpdp_edge *edges, const
     if (st != MPDP_OK) return st;
     if (n == 1) return leaf_only(q, plan_out, cost_out);
     return run(q, d_ws, ws_bytes, s, 0, plan_out, cost_out, nullptr, t0, false);
+}
+
+size_t noalloc_workspace_bytes(uint32_t n) { return (n == 0 || n > 32) ? 0 : make_layout(n).total; }
+
+const uint32_t *noalloc_setup() { return binom_table(); }
+
+mpdp_status optimize_noalloc(uint32_t n, uint32_t m, const mpdp_edge *edges, const double *card, const double *sel,
+                             mpdp_cost_model cm, mpdp_status (*get_ws)(void **), size_t ws_bytes, hipStream_t s,
+                             uint32_t flags, mpdp_plan_node *plan_out, double *cost_out, mpdp_stats *stats_out) {
+    const double t0 = now_ms();
+    if (!plan_out || !cost_out) return MPDP_EINVAL;
+    if (flags & ~(uint32_t)MPDP_FLAG_ABLATE_NO_COMPACTION & ~(uint32_t)MPDP_FLAG_ABLATE_DPSUB) return MPDP_EINVAL;
+    Query q;
+    mpdp_status st = validate(n, m, edges, card, sel, cm, nullptr, q);
+    if (st != MPDP_OK) return st;
+    if (n == 1) {
+        st = leaf_only(q, plan_out, cost_out);
+        if (stats_out) {
+            std::memset(stats_out, 0, sizeof(*stats_out));
+            stats_out->ms_total = now_ms() - t0;
+        }
+        return st;
+    }
+    if (ws_bytes < make_layout(n).total) return MPDP_ETOOLARGE;
+    void *d_ws = nullptr;
+    st = get_ws(&d_ws);
+    if (st != MPDP_OK) return st;
+    return run(q, d_ws, ws_bytes, s, flags, plan_out, cost_out, stats_out, t0,
+               (flags & MPDP_FLAG_ABLATE_DPSUB) != 0, true);
 }
 
 mpdp_status optimize_units_batch(uint32_t nq, const mpdp_batch_query *queries, const mpdp_edge *edges,

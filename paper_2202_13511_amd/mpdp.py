@@ -26,7 +26,7 @@ _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 _FLAG_BATCH_ALL_TEAMS = 0x200  # test aid: every batched query that may take a team of workgroups takes one
 
 EXPORTED = ["mpdp_status_str", "mpdp_workspace_bytes", "mpdp_memo_layout", "mpdp_optimize",
-            "mpdp_optimize_ws", "mpdp_optimize_units", "mpdp_optimize_cpu", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
+            "mpdp_optimize_ws", "mpdp_noalloc_scratch_bytes", "mpdp_optimize_noalloc", "mpdp_optimize_units", "mpdp_optimize_cpu", "mpdp_batch_workspace_bytes", "mpdp_optimize_batch",
             "mpdp_optimize_batch_sched", "mpdp_batch_autotune", "mpdp_batch_graph_create", "mpdp_batch_graph_run",
             "mpdp_batch_graph_destroy",
             "mpdp_optimize_large", "mpdp_optimize_large_budget", "mpdp_large_examples", "mpdp_scorer_param_bytes", "mpdp_scorer_work_bytes", "mpdp_scorer_layout",
@@ -122,6 +122,10 @@ def load(path: str = LIB_PATH):
     L.mpdp_optimize.restype = ctypes.c_int
     L.mpdp_optimize_ws.argtypes = common + [vp, sz, vp, u32] + outs
     L.mpdp_optimize_ws.restype = ctypes.c_int
+    L.mpdp_noalloc_scratch_bytes.argtypes = []
+    L.mpdp_noalloc_scratch_bytes.restype = sz
+    L.mpdp_optimize_noalloc.argtypes = common + [vp, u32] + outs
+    L.mpdp_optimize_noalloc.restype = ctypes.c_int
     L.mpdp_optimize_cpu.argtypes = common + [u32] + outs
     L.mpdp_optimize_cpu.restype = ctypes.c_int
     L.mpdp_optimize_units.argtypes = common[:5] + [f64p, ctypes.c_int, vp, sz, vp, u32] + outs
@@ -276,6 +280,29 @@ def mpdp_optimize_ws(query, cost_model: int, ws, stream=None, flags: int = 0) ->
     st = load().mpdp_optimize_ws(int(n), m, ep, cp, sp, int(cost_model), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel() * ws.element_size(), ctypes.c_void_p(stream.cuda_stream),
                                  int(flags), plan, ctypes.byref(cost), ctypes.byref(stats))
+    if st != MPDP_OK:
+        raise MpdpError(st, mpdp_status_str(st))
+    return _result(n, plan, cost, stats)
+
+
+MPDP_NOALLOC_MAX_REL = 20
+
+
+def mpdp_noalloc_scratch_bytes() -> int:
+    return int(load().mpdp_noalloc_scratch_bytes())
+
+
+def mpdp_optimize_noalloc(query, cost_model: int, stream=None, flags: int = 0) -> Result:
+    """mpdp_optimize_ws without a workspace: the library's fixed device array
+    (n <= MPDP_NOALLOC_MAX_REL); nothing is allocated by the call."""
+    n, edges, card, sel = _args(query)
+    keep, m, ep, cp, sp = _marshal(n, edges, card, sel)
+    sp_handle = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    plan = (mpdp_plan_node * max(2 * n - 1, 1))()
+    cost = ctypes.c_double()
+    stats = mpdp_stats()
+    st = load().mpdp_optimize_noalloc(int(n), m, ep, cp, sp, int(cost_model), sp_handle, int(flags), plan,
+                                      ctypes.byref(cost), ctypes.byref(stats))
     if st != MPDP_OK:
         raise MpdpError(st, mpdp_status_str(st))
     return _result(n, plan, cost, stats)
