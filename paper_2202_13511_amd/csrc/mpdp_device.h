@@ -255,24 +255,42 @@ __device__ __forceinline__ void offer_if(bool on, Key &best, double cost, uint32
 // v's lowest smaller neighbour comes from the (card, sel) pair of v (times
 // an exact 1.0 when that neighbour is outside S); v's other smaller
 // neighbours in S, which a tree seldom has, go through the sel row.
+// Members go in batches of four whose LDS reads are all issued before the
+// products use them (slots past k read relation 31's entries, C(31, i) and
+// a (1.0, 1.0) pair, and are masked); the products stay in member order.
 __device__ __forceinline__ void tree_bsum_card(const LdsGraph &L, uint32_t S, uint32_t k, uint32_t &bsum,
                                                double &cardS) {
+    constexpr int kB = 4;
     double c = 1.0;
     uint32_t b = 0;
     uint32_t T = S;
-    for (uint32_t i = 0; i < k; ++i) {
-        const int v = ctz32(T);
-        T &= T - 1;
-        b += L.binom[v * 33 + i];
-        const double2 cs = *reinterpret_cast<const double2 *>(L.csel[v]);
-        const uint2 lo = *reinterpret_cast<const uint2 *>(L.lo[v]);
-        c = c * cs.x;
-        c = c * ((S & lo.x) ? cs.y : 1.0);
-        const uint32_t rest = lo.y & S;
-        if (rest) {
-            const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
-            for (uint32_t U = rest; U; U &= U - 1)
-                c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+    for (uint32_t i0 = 0; i0 < k; i0 += kB) {
+        int vv[kB];
+        uint32_t bb[kB];
+        double2 cs[kB];
+        uint2 lo[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            vv[u] = ctz32(T | 0x80000000u);
+            T &= T - 1;
+            bb[u] = L.binom[vv[u] * 33 + i0 + u];
+            cs[u] = *reinterpret_cast<const double2 *>(L.csel[vv[u]]);
+            lo[u] = *reinterpret_cast<const uint2 *>(L.lo[vv[u]]);
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (i0 + (uint32_t)u < k) {  // uniform: every set of the level has k members
+                b += bb[u];
+                c = c * cs[u].x;
+                c = c * ((S & lo[u].x) ? cs[u].y : 1.0);
+                const uint32_t rest = lo[u].y & S;
+                if (rest) {
+                    const int v = vv[u];
+                    const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+                    for (uint32_t U = rest; U; U &= U - 1)
+                        c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+                }
+            }
         }
     }
     bsum = b;
@@ -298,42 +316,75 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
         // 31's entries, which exist, and are masked); all LDS reads of the
         // batch are issued before any is used
         uint32_t Av[kPairBatch], rk[kPairBatch], ba[kPairBatch], bb[kPairBatch];
+        int mv[kPairBatch];
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
             const uint32_t i = i0 + (uint32_t)u;
             const bool live = i < k;
             const int m = ctz32(T | 0x80000000u);
             T &= T - 1;
+            mv[u] = m;
             bb[u] = L.binom[m * 33 + i];
             ba[u] = L.binom[m * 33 + i + 1];
             const uint32_t par = L.pbit[m], below = L.desc[m];
             Av[u] = (live & ((S & par) != 0)) ? (below & S) : 0u;
         }
+        uint32_t multi = 0;  // a side of two or more relations in this batch
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
             // a slot past the last member gathers entry 0
             pb += bb[u];
             rk[u] = (i0 + (uint32_t)u < k) ? pa + (bsum - pb) : 0u;
             pa += ba[u];
+            multi |= Av[u] & (Av[u] - 1u);
         }
         double cA[kPairBatch], cB[kPairBatch], kA[kPairBatch], kB[kPairBatch];
+        if (__ballot(multi != 0) == 0) {
+            // every pair of the batch, on every lane, splits off one relation
+            // (always so on a star): one straight run of gathers, all in
+            // flight together
 #pragma unroll
-        for (int u = 0; u < kPairBatch; ++u) {
-            const uint32_t A = Av[u];
-            if ((A & (A - 1)) == 0) {  // a singleton, or the empty slot
+            for (int u = 0; u < kPairBatch; ++u) {
                 cB[u] = cost_km1[rk[u]];
                 if (CM != MPDP_COST_COUT) kB[u] = card_km1[rk[u]];
-                const int m = ctz32(A | 0x80000000u);
-                cA[u] = L.bcost[m & 31];
-                kA[u] = L.card[m & 31];
-            } else {
-                const uint64_t ia = memo_index(L, A), ib = memo_index(L, S ^ A);
-                cA[u] = M.cost[ia];
-                cB[u] = M.cost[ib];
+            }
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                const int m = mv[u] & 31;
+                cA[u] = L.bcost[m];
+                kA[u] = L.card[m];
+            }
+        } else {
+            // some side has two or more relations: its memo index and its
+            // complement's come from colex sums (LDS only); then every slot
+            // gathers both sides in one straight run (a singleton side
+            // gathers its partner's entry again and takes its own values
+            // from LDS)
+            uint64_t ia[kPairBatch], ib[kPairBatch];
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                const uint32_t A = Av[u];
+                const bool single = (A & (A - 1)) == 0;
+                ib[u] = single ? L.loff[k - 1] + rk[u] : memo_index(L, S ^ A);
+                ia[u] = single ? ib[u] : memo_index(L, A);
+            }
+            double gA[kPairBatch], hA[kPairBatch];
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                cB[u] = M.cost[ib[u]];
+                gA[u] = M.cost[ia[u]];
                 if (CM != MPDP_COST_COUT) {
-                    kA[u] = M.card[ia];
-                    kB[u] = M.card[ib];
+                    kB[u] = M.card[ib[u]];
+                    hA[u] = M.card[ia[u]];
                 }
+            }
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                const uint32_t A = Av[u];
+                const bool single = (A & (A - 1)) == 0;
+                const int m = ctz32(A | 0x80000000u) & 31;
+                cA[u] = single ? L.bcost[m] : gA[u];
+                if (CM != MPDP_COST_COUT) kA[u] = single ? L.card[m] : hA[u];
             }
         }
 #pragma unroll
