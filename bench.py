@@ -29,7 +29,8 @@ configs    the paper-shaped single queries: star 12, snowflake 25 (both
            models), cycle of 20-30 relations plus 5-15 chords, clique 18:
            optimize time median / p99 over the seeds, ccp pairs per second
 ablations  the same optimizer with DPSUB's vertex-based candidates on the GPU,
-           and the tree kernel without its LDS compaction (results unchanged)
+           the tree kernel without its LDS compaction, and with prune not
+           fused into evaluate (results unchanged)
 cpu_allcores  the library's multi-threaded CPU MPDP on the star, on one
            GPU's share of the host's cores (16 threads at most; the host's
            core count and CPU model are recorded), next to the single-thread
@@ -458,7 +459,7 @@ def bench_configs(mpdp, workloads, np, dev):
 
 
 def bench_ablations(mpdp, workloads, dev, reps=5):
-    """Optimize time (min of reps) with and without the two enhancements."""
+    """Optimize time (min of reps) with and without the enhancements."""
     import torch
 
     def best_ms(q, flags):
@@ -474,11 +475,13 @@ def bench_ablations(mpdp, workloads, dev, reps=5):
         torch.cuda.empty_cache()
         return min(ts), st
 
-    out = {"no_compaction": {}, "dpsub": {}}
+    out = {"no_compaction": {}, "unfused_prune": {}, "dpsub": {}}
     for q in (workloads.star(25, 0), workloads.snowflake(25, 0)):
         a, _ = best_ms(q, 0)
         b, _ = best_ms(q, mpdp.MPDP_FLAG_ABLATE_NO_COMPACTION)
         out["no_compaction"][q.name] = {"mpdp_ms": a, "ablated_ms": b, "slowdown": b / a}
+        b, _ = best_ms(q, mpdp.MPDP_FLAG_ABLATE_UNFUSED_PRUNE)
+        out["unfused_prune"][q.name] = {"mpdp_ms": a, "ablated_ms": b, "slowdown": b / a}
     for q in (workloads.star(20, 0), workloads.snowflake(20, 1), workloads.clique(14, 0)):
         a, sa = best_ms(q, 0)
         b, sb = best_ms(q, mpdp.MPDP_FLAG_ABLATE_DPSUB)

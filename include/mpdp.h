@@ -97,9 +97,16 @@ typedef struct {
  *            every subset holding its lowest relation, CCP-checked) instead of
  *            Alg. 2/3's block-local ones; evaluated_pairs counts 2^|S| - 2 per set
  * NO_COMPACTION  tree joins: each lane evaluates the connected candidates it
- *            unranked instead of compacting them through the wave's LDS ring */
+ *            unranked instead of compacting them through the wave's LDS ring
+ * UNFUSED_PRUNE  tree joins: prune is not fused into evaluate (Section 5,
+ *            "Enhancements"): the evaluate kernel writes the key of every
+ *            pair to global memory and a separate prune kernel reduces each
+ *            set's keys and writes its memo entry; the library allocates the
+ *            key buffer (16 bytes per pair of the widest level) once per
+ *            device and keeps it */
 #define MPDP_FLAG_ABLATE_DPSUB 2u
 #define MPDP_FLAG_ABLATE_NO_COMPACTION 4u
+#define MPDP_FLAG_ABLATE_UNFUSED_PRUNE 8u
 
 /* Status string for an mpdp_status value (static storage, never NULL). */
 const char *mpdp_status_str(mpdp_status s);

@@ -24,6 +24,9 @@ namespace {
 
 constexpr int kBatchBlock = 512;
 constexpr int kBW = kBatchBlock / 64;
+// members per gather batch of a tree set: three keeps the kernel (every
+// path of a query inlined, 128 registers per lane) from spilling far more
+constexpr int kBatchPairBatch = 3;
 constexpr unsigned long long kTeamWaitTicks = 200000000ull;  // 2 s of the 100 MHz device clock
 
 // The workgroups of a team meet here for the `phase`-th time.  Every wave
@@ -74,12 +77,12 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
     const double *SL = sels + Q.edge_off;
     if (t < kMaxRel) {
         L.adj[t] = 0;
-        L.pbit[t] = 0;
+        L.pd[t][0] = 0;
         L.lo[t][0] = 0;
         L.lo[t][1] = 0;
         L.csel[t][0] = t < n ? C[t] : 1.0;
         L.csel[t][1] = 1.0;
-        L.desc[t] = 1u << t;
+        L.pd[t][1] = 1u << t;
         L.card[t] = t < n ? C[t] : 1.0;
         if (t >= n) L.bcost[t] = 0.0;
         else if (bcosts) L.bcost[t] = bcosts[Q.card_off + t];  // planned intermediate results
@@ -133,8 +136,8 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
                     order[tail++] = c;
                 }
             }
-            for (uint32_t i = 1; i < tail; ++i) L.pbit[order[i]] = 1u << parent[order[i]];
-            for (uint32_t i = tail - 1; i > 0; --i) L.desc[parent[order[i]]] |= L.desc[order[i]];
+            for (uint32_t i = 1; i < tail; ++i) L.pd[order[i]][0] = 1u << parent[order[i]];
+            for (uint32_t i = tail - 1; i > 0; --i) L.pd[parent[order[i]]][1] |= L.pd[order[i]][1];
         }
     }
     __syncthreads();
@@ -143,7 +146,7 @@ __device__ void build_image(LdsGraph &L, const BatchQueryDev &Q, const uint32_t 
             const uint32_t byte = i >> 8, x = i & 255u;
             uint32_t c = 0;
             for (uint32_t v = 1; v < n; ++v)
-                if (L.pbit[v] & (x << (8u * byte))) c |= 1u << v;
+                if (L.pd[v][0] & (x << (8u * byte))) c |= 1u << v;
             L.ch[byte][x] = c;
         }
         __syncthreads();
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                                                        TeamRec *teams, BatchCounters *bc) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ uint32_t rings[kBW][kRing];
-    __shared__ uint32_t ring_ranks[kBW][kRing];
+    __shared__ uint32_t ring_bsums[kBW][kRing];
     __shared__ WaveScratch WS[kBW];
     __shared__ SetBlocks hsb;
     __shared__ Key hkeys[kBW];
@@ -250,16 +253,16 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 uint32_t found;
                 switch (Q.sched & kSchedChunkMask) {  // consecutive ranks per lane
                     case 0:
-                        found = level_tree_wave<CM, 1>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 63) / 64,
-                                                       rings[wave], ring_ranks[wave], lane);
+                        found = level_tree_wave<CM, 1, true, kRing, 1, kBatchPairBatch>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 63) / 64,
+                                                       rings[wave], ring_bsums[wave], lane);
                         break;
                     case 1:
-                        found = level_tree_wave<CM, 2>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 127) / 128,
-                                                       rings[wave], ring_ranks[wave], lane);
+                        found = level_tree_wave<CM, 2, true, kRing, 1, kBatchPairBatch>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 127) / 128,
+                                                       rings[wave], ring_bsums[wave], lane);
                         break;
                     default:
-                        found = level_tree_wave<CM, 4>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 255) / 256,
-                                                       rings[wave], ring_ranks[wave], lane);
+                        found = level_tree_wave<CM, 4, true, kRing, 1, kBatchPairBatch>(L, M, (int)n, k, ncand, wave, kBW, (ncand + 255) / 256,
+                                                       rings[wave], ring_bsums[wave], lane);
                         break;
                 }
                 if (lane == 0 && found) atomicAdd(&s_level, found);

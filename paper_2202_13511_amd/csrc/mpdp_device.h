@@ -15,13 +15,18 @@ namespace {
 constexpr int kBlock = 256;         // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kFilterChunk = 16;    // consecutive ranks per lane in k_filter (<= 31)
-constexpr int kTreeChunkMax = 4;    // consecutive ranks per lane in k_level_tree (1, 2 or 4)
-constexpr int kRing = 384;          // per-wave ring of connected sets (>= 63 + 64 * kTreeChunkMax)
+// consecutive ranks per lane in k_level_tree: 1, 2 or 4, and 8 on the
+// largest levels under C_out (one unrank per eight candidates)
+constexpr int kTreeChunkMax = 8;
+constexpr int kRing = 384;          // per-wave ring of the batched kernel (chunks up to 4, one set per lane)
 constexpr uint32_t kPersistGrid = 1024;  // workgroups that keep the whole chip busy (4 per CU)
 // Tree levels under C_out gather one word per pair: three workgroups per CU
 // leave fewer gathers in flight and lose fewer of them from the caches
 // (PG-like's two words per pair want the fourth).
-constexpr uint32_t kPersistGridCout = 768;
+#ifndef MPDP_TREE_GRID_COUT
+#define MPDP_TREE_GRID_COUT 768
+#endif
+constexpr uint32_t kPersistGridCout = MPDP_TREE_GRID_COUT;
 // Tree levels with at least kTreeSplitMinK members per set (two or more
 // batches of gathers for one lane) and at most kTreeSplitMaxCand candidates
 // are too small to hide a lane's serial gathers: kTreeSplitLanes lanes take
@@ -33,7 +38,28 @@ constexpr uint32_t kHeavyChunks = 256;   // above this many 16-candidate chunks 
 constexpr int kHeavyBlock = 1024;        // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
 
-static_assert(kRing >= 63 + 64 * kTreeChunkMax, "ring too small");
+// Sets a lane evaluates at once in k_level_tree (independent chains,
+// interleaved): two under C_out, one under PG-like, whose gathers and
+// costs of two sets at once need more registers than pay off.
+#ifndef MPDP_TREE_SETS_PER_LANE_COUT
+#define MPDP_TREE_SETS_PER_LANE_COUT 2
+#endif
+constexpr int kTreeSetsMax = MPDP_TREE_SETS_PER_LANE_COUT;
+template <int CM>
+constexpr int tree_sets_per_lane() { return CM == MPDP_COST_COUT ? MPDP_TREE_SETS_PER_LANE_COUT : 1; }
+// per-wave ring of k_level_tree: room for the sets a drain leaves (fewer
+// than 64 per lane) and one pass of appends (at most 64 * chunk)
+constexpr int kTreeRing = 640;
+static_assert(kTreeRing >= 64 * kTreeSetsMax - 1 + 64 * kTreeChunkMax, "ring too small");
+// members per batch of the tree pair loop (gathers in flight per lane; the
+// batched kernel, which keeps much more state live, takes three) and of the
+// card(S) pass (LDS reads in flight)
+#ifndef MPDP_TREE_PAIR_BATCH
+#define MPDP_TREE_PAIR_BATCH 4
+#endif
+#ifndef MPDP_TREE_CARD_BATCH
+#define MPDP_TREE_CARD_BATCH 4
+#endif
 
 // ---------------------------------------------------------------- bitmaps
 
@@ -129,6 +155,36 @@ __device__ __forceinline__ uint32_t colex_unrank(const uint32_t *binom, int n, i
     return S;
 }
 
+// colex_unrank that also returns bsum = sum over the members s_i of S of
+// C(s_i, i) (i from 0), read with C(c, i) as its neighbour in the table.
+// For the same-popcount successor S' of S, bsum(S') = bsum(S) + t - 1
+// where t is the length of the lowest run of ones of S: the run's members
+// p .. p+t-1 at places 0 .. t-1 contribute sum_{i<t} C(p+i, i) = C(p+t, t-1)
+// (hockey stick), which is exactly what member p+t at place t-1 contributes
+// to S', whose places 0 .. t-2 hold members 0 .. t-2 at C(i, i) = 1 each.
+__device__ __forceinline__ uint32_t colex_unrank_b(const uint32_t *binom, int n, int k, uint32_t r, uint32_t &bsum) {
+    uint32_t S = 0, b = 0;
+    int i = k;
+#pragma unroll 4
+    for (int c = n - 1; c >= 0; --c) {
+        const uint32_t at = (uint32_t)(c * 33 + (i > 0 ? i - 1 : 0));
+        const uint32_t t0 = binom[at], t1 = binom[at + 1];  // C(c, i - 1), C(c, i)
+        const bool take = (i > 0) & (t1 <= r);
+        r -= take ? t1 : 0u;
+        b += take ? t0 : 0u;
+        S |= take ? (1u << c) : 0u;
+        i -= take ? 1 : 0;
+    }
+    bsum = b;
+    return S;
+}
+
+// bsum of the same-popcount successor of S (see colex_unrank_b).
+__device__ __forceinline__ uint32_t next_bsum(uint32_t S, uint32_t bsum) {
+    const uint32_t run = ~(S >> ctz32(S));
+    return bsum + (uint32_t)ctz32(run | 0x80000000u) - 1u;
+}
+
 // ---------------------------------------------------------------- cost
 
 // card(S): product over S ascending of card[v] and of the selectivities of
@@ -221,19 +277,8 @@ __device__ __forceinline__ void eval_vals(uint32_t A, uint32_t B, double cA, dou
 }
 
 
-// Alg. 2 for one connected S of a tree join graph.  With the tree rooted at
-// relation 0, removing the edge (parent(c), c) of G[S] gives the pair
-// (desc(c) & S, S minus that) for every c in S whose parent is in S, which
-// is every member but the topmost one.  When desc(c) & S = {c} the
-// complement's colex rank follows from prefix sums,
-// rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and the
-// singleton's cost and card come from LDS.
-//
-// Every set of the level has k members and k is the same on all lanes, so
-// the member loops run a uniform k times (scalar branches only).  Members
-// go in batches of kPairBatch whose memo gathers are all issued before any
-// is used; the topmost member stays in its batch as an empty slot (A = 0)
-// that gathers a harmless singleton and offers nothing.
+// Key order with the operator compared only where it can decide (not under
+// C_out, whose offers all carry one operator).
 template <int CM>
 __device__ __forceinline__ bool key_less_sel(unsigned long long ac, uint32_t al, uint32_t aop, const Key &b) {
     if (CM == MPDP_COST_COUT) return (ac < b.c) | ((ac == b.c) & (al < b.l));
@@ -249,164 +294,322 @@ __device__ __forceinline__ void offer_if(bool on, Key &best, double cost, uint32
     if (CM != MPDP_COST_COUT) best.op = take ? op : best.op;
 }
 
-// One pass over the k members of a tree-inducing S: bsum = sum of C(s_i, i),
+// One pass over the k members of R tree-inducing sets S[r] of one level
+// (R independent chains per lane, interleaved): bsum = sum of C(s_i, i),
 // and card(S) in card_of's order (members ascending, each card then the
 // selectivities of its edges to smaller members, ascending).  The edge to
 // v's lowest smaller neighbour comes from the (card, sel) pair of v (times
 // an exact 1.0 when that neighbour is outside S); v's other smaller
 // neighbours in S, which a tree seldom has, go through the sel row.
-// Members go in batches of four whose LDS reads are all issued before the
-// products use them (slots past k read relation 31's entries, C(31, i) and
-// a (1.0, 1.0) pair, and are masked); the products stay in member order.
-__device__ __forceinline__ void tree_bsum_card(const LdsGraph &L, uint32_t S, uint32_t k, uint32_t &bsum,
-                                               double &cardS) {
-    constexpr int kB = 4;
-    double c = 1.0;
-    uint32_t b = 0;
-    uint32_t T = S;
-    for (uint32_t i0 = 0; i0 < k; i0 += kB) {
-        int vv[kB];
-        uint32_t bb[kB];
-        double2 cs[kB];
-        uint2 lo[kB];
+// Members go in batches whose LDS reads are all issued before the products
+// use them (slots past k read relation 31's entries, C(31, i) and a
+// (1.0, 1.0) pair, and are masked); the products stay in member order.
+template <int R>
+__device__ __forceinline__ void tree_bsum_card_n(const LdsGraph &L, const uint32_t *S, uint32_t k, uint32_t *bsum,
+                                                 double *cardS) {
+    constexpr int kB = MPDP_TREE_CARD_BATCH;
+    double c[R];
+    uint32_t b[R], T[R];
 #pragma unroll
-        for (int u = 0; u < kB; ++u) {
-            vv[u] = ctz32(T | 0x80000000u);
-            T &= T - 1;
-            bb[u] = L.binom[vv[u] * 33 + i0 + u];
-            cs[u] = *reinterpret_cast<const double2 *>(L.csel[vv[u]]);
-            lo[u] = *reinterpret_cast<const uint2 *>(L.lo[vv[u]]);
-        }
+    for (int r = 0; r < R; ++r) { c[r] = 1.0; b[r] = 0; T[r] = S[r]; }
+    for (uint32_t i0 = 0; i0 < k; i0 += kB) {
+        int vv[R][kB];
+        uint32_t bb[R][kB];
+        double2 cs[R][kB];
+        uint2 lo[R][kB];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                vv[r][u] = ctz32(T[r] | 0x80000000u);
+                T[r] &= T[r] - 1;
+                bb[r][u] = L.binom[vv[r][u] * 33 + i0 + u];
+                cs[r][u] = *reinterpret_cast<const double2 *>(L.csel[vv[r][u]]);
+                lo[r][u] = *reinterpret_cast<const uint2 *>(L.lo[vv[r][u]]);
+            }
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             if (i0 + (uint32_t)u < k) {  // uniform: every set of the level has k members
-                b += bb[u];
-                c = c * cs[u].x;
-                c = c * ((S & lo[u].x) ? cs[u].y : 1.0);
-                const uint32_t rest = lo[u].y & S;
-                if (rest) {
-                    const int v = vv[u];
-                    const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
-                    for (uint32_t U = rest; U; U &= U - 1)
-                        c = c * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    b[r] += bb[r][u];
+                    c[r] = c[r] * cs[r][u].x;
+                    c[r] = c[r] * ((S[r] & lo[r][u].x) ? cs[r][u].y : 1.0);
+                    const uint32_t rest = lo[r][u].y & S[r];
+                    if (rest) {
+                        const int v = vv[r][u];
+                        const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+                        for (uint32_t U = rest; U; U &= U - 1)
+                            c[r] = c[r] * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+                    }
                 }
             }
         }
     }
-    bsum = b;
-    cardS = c < 1.0 ? 1.0 : c;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        bsum[r] = b[r];
+        cardS[r] = c[r] < 1.0 ? 1.0 : c[r];
+    }
 }
 
-template <int CM>
-__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t rank,
-                                              uint32_t k, uint64_t off_k, const double *__restrict__ cost_km1,
-                                              const double *__restrict__ card_km1) {
-    constexpr int kPairBatch = 4;
-    // S's own colex rank comes with it from the filter
-    uint32_t bsum;
-    double cardS;
-    tree_bsum_card(L, S, k, bsum, cardS);
+__device__ __forceinline__ void tree_bsum_card(const LdsGraph &L, uint32_t S, uint32_t k, uint32_t &bsum,
+                                               double &cardS) {
+    tree_bsum_card_n<1>(L, &S, k, &bsum, &cardS);
+}
+
+// card(S) of R tree-inducing sets of one level, as tree_bsum_card_n without
+// the colex sums.
+template <int R>
+__device__ __forceinline__ void tree_card_n(const LdsGraph &L, const uint32_t *S, uint32_t k, double *cardS) {
+    constexpr int kB = MPDP_TREE_CARD_BATCH;
+    double c[R];
+    uint32_t T[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { c[r] = 1.0; T[r] = S[r]; }
+    for (uint32_t i0 = 0; i0 < k; i0 += kB) {
+        int vv[R][kB];
+        double2 cs[R][kB];
+        uint2 lo[R][kB];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                vv[r][u] = ctz32(T[r] | 0x80000000u);
+                T[r] &= T[r] - 1;
+                cs[r][u] = *reinterpret_cast<const double2 *>(L.csel[vv[r][u]]);
+                lo[r][u] = *reinterpret_cast<const uint2 *>(L.lo[vv[r][u]]);
+            }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (i0 + (uint32_t)u < k) {  // uniform: every set of the level has k members
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    c[r] = c[r] * cs[r][u].x;
+                    c[r] = c[r] * ((S[r] & lo[r][u].x) ? cs[r][u].y : 1.0);
+                    const uint32_t rest = lo[r][u].y & S[r];
+                    if (rest) {
+                        const int v = vv[r][u];
+                        const uint32_t lower = L.adj[v] & ((1u << v) - 1u);
+                        for (uint32_t U = rest; U; U &= U - 1)
+                            c[r] = c[r] * L.sel[L.selrow[v] + (uint32_t)popc32(lower & (lowbit(U) - 1u))];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) cardS[r] = c[r] < 1.0 ? 1.0 : c[r];
+}
+
+// Alg. 2 for R connected sets of one level per lane (R independent
+// chains, interleaved; see eval_tree_set for one).  Every set has k members
+// and k is the same on all lanes, so the member loops run a uniform k times
+// (scalar branches only).  Members go in batches of kPairBatch whose memo
+// gathers are all issued before any is used; the topmost member stays in
+// its batch as an empty slot (A = 0) that gathers a harmless singleton and
+// offers nothing.
+// Where eval_tree_sets leaves its results: fused (the default), each set's
+// best key goes to the memo; unfused (the prune ablation), every pair's key
+// goes to keys[slot[r] * k + member index] and the set's record to
+// recs[slot[r]], for a separate prune kernel.
+struct TreeSink {
+    PairKey *keys = nullptr;
+    PruneRec *recs = nullptr;
+    uint32_t slot[2] = {0, 0};
+};
+
+template <int CM, int R, int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false>
+__device__ __forceinline__ void eval_tree_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *S,
+                                               const uint32_t *bsum, uint32_t k, uint64_t off_k,
+                                               const double *__restrict__ cost_km1,
+                                               const double *__restrict__ card_km1,
+                                               const TreeSink &sink = TreeSink{}) {
+    // each set's bsum = sum of C(s_i, i) comes with it from the filter, and
+    // its own colex rank sum C(s_i, i + 1) accumulates in pa below
+    double cardS[R];
+    tree_card_n<R>(L, S, k, cardS);
     // C_out offers carry one operator, so the running best starts with it
     // and the operator never decides
-    Key best = worst_key();
-    if (CM == MPDP_COST_COUT) best.op = MPDP_OP_JOIN;
-    uint32_t pa = 0, pb = 0, T = S;
+    Key best[R];
+    uint32_t pa[R], pb[R], T[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        best[r] = worst_key();
+        if (CM == MPDP_COST_COUT) best[r].op = MPDP_OP_JOIN;
+        pa[r] = pb[r] = 0;
+        T[r] = S[r];
+    }
     for (uint32_t i0 = 0; i0 < k; i0 += kPairBatch) {
         // members i0 .. i0 + kPairBatch - 1 (slots past k read relation
         // 31's entries, which exist, and are masked); all LDS reads of the
         // batch are issued before any is used
-        uint32_t Av[kPairBatch], rk[kPairBatch], ba[kPairBatch], bb[kPairBatch];
-        int mv[kPairBatch];
+        uint32_t Av[R][kPairBatch], rk[R][kPairBatch], ba[R][kPairBatch], bb[R][kPairBatch];
+        int mv[R][kPairBatch];
 #pragma unroll
-        for (int u = 0; u < kPairBatch; ++u) {
-            const uint32_t i = i0 + (uint32_t)u;
-            const bool live = i < k;
-            const int m = ctz32(T | 0x80000000u);
-            T &= T - 1;
-            mv[u] = m;
-            bb[u] = L.binom[m * 33 + i];
-            ba[u] = L.binom[m * 33 + i + 1];
-            const uint32_t par = L.pbit[m], below = L.desc[m];
-            Av[u] = (live & ((S & par) != 0)) ? (below & S) : 0u;
-        }
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                const uint32_t i = i0 + (uint32_t)u;
+                const bool live = i < k;
+                const int m = ctz32(T[r] | 0x80000000u);
+                T[r] &= T[r] - 1;
+                mv[r][u] = m;
+                bb[r][u] = L.binom[m * 33 + i];
+                ba[r][u] = L.binom[m * 33 + i + 1];
+                const uint2 pd = *reinterpret_cast<const uint2 *>(L.pd[m]);  // parent bit, subtree
+                const uint32_t on = (uint32_t)(live & ((S[r] & pd.x) != 0));
+                Av[r][u] = pd.y & S[r] & (0u - on);
+            }
         uint32_t multi = 0;  // a side of two or more relations in this batch
 #pragma unroll
-        for (int u = 0; u < kPairBatch; ++u) {
-            // a slot past the last member gathers entry 0
-            pb += bb[u];
-            rk[u] = (i0 + (uint32_t)u < k) ? pa + (bsum - pb) : 0u;
-            pa += ba[u];
-            multi |= Av[u] & (Av[u] - 1u);
-        }
-        double cA[kPairBatch], cB[kPairBatch], kA[kPairBatch], kB[kPairBatch];
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                // a slot past the last member gathers entry 0
+                const bool live = i0 + (uint32_t)u < k;
+                pb[r] += bb[r][u];
+                rk[r][u] = live ? pa[r] + (bsum[r] - pb[r]) : 0u;
+                pa[r] += live ? ba[r][u] : 0u;
+                multi |= Av[r][u] & (Av[r][u] - 1u);
+            }
+        double cA[R][kPairBatch], cB[R][kPairBatch], kA[R][kPairBatch], kB[R][kPairBatch];
         if (__ballot(multi != 0) == 0) {
             // every pair of the batch, on every lane, splits off one relation
             // (always so on a star): one straight run of gathers, all in
             // flight together
 #pragma unroll
-            for (int u = 0; u < kPairBatch; ++u) {
-                cB[u] = cost_km1[rk[u]];
-                if (CM != MPDP_COST_COUT) kB[u] = card_km1[rk[u]];
-            }
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int u = 0; u < kPairBatch; ++u) {
-                const int m = mv[u] & 31;
-                cA[u] = L.bcost[m];
-                kA[u] = L.card[m];
-            }
+                for (int u = 0; u < kPairBatch; ++u) {
+                    cB[r][u] = cost_km1[rk[r][u]];
+                    if (CM != MPDP_COST_COUT) kB[r][u] = card_km1[rk[r][u]];
+                }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < kPairBatch; ++u) {
+                    const int m = mv[r][u] & 31;
+                    cA[r][u] = L.bcost[m];
+                    kA[r][u] = L.card[m];
+                }
         } else {
             // some side has two or more relations: its memo index and its
             // complement's come from colex sums (LDS only); then every slot
             // gathers both sides in one straight run (a singleton side
             // gathers its partner's entry again and takes its own values
             // from LDS)
-            uint64_t ia[kPairBatch], ib[kPairBatch];
+            uint64_t ia[R][kPairBatch], ib[R][kPairBatch];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < kPairBatch; ++u) {
+                    const uint32_t A = Av[r][u];
+                    const bool single = (A & (A - 1)) == 0;
+                    ib[r][u] = single ? L.loff[k - 1] + rk[r][u] : memo_index(L, S[r] ^ A);
+                    ia[r][u] = single ? ib[r][u] : memo_index(L, A);
+                }
+            double gA[R][kPairBatch], hA[R][kPairBatch];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < kPairBatch; ++u) {
+                    cB[r][u] = M.cost[ib[r][u]];
+                    gA[r][u] = M.cost[ia[r][u]];
+                    if (CM != MPDP_COST_COUT) {
+                        kB[r][u] = M.card[ib[r][u]];
+                        hA[r][u] = M.card[ia[r][u]];
+                    }
+                }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < kPairBatch; ++u) {
+                    const uint32_t A = Av[r][u];
+                    const bool single = (A & (A - 1)) == 0;
+                    const int m = ctz32(A | 0x80000000u) & 31;
+                    cA[r][u] = single ? L.bcost[m] : gA[r][u];
+                    if (CM != MPDP_COST_COUT) kA[r][u] = single ? L.card[m] : hA[r][u];
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int u = 0; u < kPairBatch; ++u) {
-                const uint32_t A = Av[u];
-                const bool single = (A & (A - 1)) == 0;
-                ib[u] = single ? L.loff[k - 1] + rk[u] : memo_index(L, S ^ A);
-                ia[u] = single ? ib[u] : memo_index(L, A);
-            }
-            double gA[kPairBatch], hA[kPairBatch];
-#pragma unroll
-            for (int u = 0; u < kPairBatch; ++u) {
-                cB[u] = M.cost[ib[u]];
-                gA[u] = M.cost[ia[u]];
-                if (CM != MPDP_COST_COUT) {
-                    kB[u] = M.card[ib[u]];
-                    hA[u] = M.card[ia[u]];
+                const uint32_t A = Av[r][u], B = S[r] ^ A;
+                const bool on = A != 0;
+                const double base = cA[r][u] + cB[r][u];
+                if (kUnfused) {
+                    // this pair's best orientation alone, written out
+                    Key one = worst_key();
+                    if (CM == MPDP_COST_COUT) {
+                        one.op = MPDP_OP_JOIN;
+                        offer_if<CM>(on, one, base + cardS[r], A < B ? A : B, MPDP_OP_JOIN);
+                    } else {
+                        const double out = 0.01 * cardS[r];
+                        const double hjA = ((base + 0.0125 * kB[r][u]) + 0.0025 * kA[r][u]) + out;
+                        const double nlA = (base + (0.0025 * kA[r][u]) * kB[r][u]) + out;
+                        const double hjB = ((base + 0.0125 * kA[r][u]) + 0.0025 * kB[r][u]) + out;
+                        const double nlB = (base + (0.0025 * kB[r][u]) * kA[r][u]) + out;
+                        const bool hA = hjA <= nlA, hB = hjB <= nlB;
+                        offer_if<CM>(on, one, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                        offer_if<CM>(on, one, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                    }
+                    if (i0 + (uint32_t)u < k)
+                        sink.keys[(uint64_t)sink.slot[r] * k + i0 + (uint32_t)u] = PairKey{one.c, one.l, one.op};
+                    continue;
+                }
+                if (CM == MPDP_COST_COUT) {
+                    offer_if<CM>(on, best[r], base + cardS[r], A < B ? A : B, MPDP_OP_JOIN);
+                } else {
+                    const double out = 0.01 * cardS[r];
+                    const double hjA = ((base + 0.0125 * kB[r][u]) + 0.0025 * kA[r][u]) + out;  // A outer, B hashed
+                    const double nlA = (base + (0.0025 * kA[r][u]) * kB[r][u]) + out;
+                    const double hjB = ((base + 0.0125 * kA[r][u]) + 0.0025 * kB[r][u]) + out;  // B outer, A hashed
+                    const double nlB = (base + (0.0025 * kB[r][u]) * kA[r][u]) + out;
+                    const bool hA = hjA <= nlA, hB = hjB <= nlB;
+                    offer_if<CM>(on, best[r], hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                    offer_if<CM>(on, best[r], hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
                 }
             }
-#pragma unroll
-            for (int u = 0; u < kPairBatch; ++u) {
-                const uint32_t A = Av[u];
-                const bool single = (A & (A - 1)) == 0;
-                const int m = ctz32(A | 0x80000000u) & 31;
-                cA[u] = single ? L.bcost[m] : gA[u];
-                if (CM != MPDP_COST_COUT) kA[u] = single ? L.card[m] : hA[u];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kPairBatch; ++u) {
-            const uint32_t A = Av[u], B = S ^ A;
-            const bool on = A != 0;
-            const double base = cA[u] + cB[u];
-            if (CM == MPDP_COST_COUT) {
-                offer_if<CM>(on, best, base + cardS, A < B ? A : B, MPDP_OP_JOIN);
-            } else {
-                const double out = 0.01 * cardS;
-                const double hjA = ((base + 0.0125 * kB[u]) + 0.0025 * kA[u]) + out;  // A outer, B hashed
-                const double nlA = (base + (0.0025 * kA[u]) * kB[u]) + out;
-                const double hjB = ((base + 0.0125 * kA[u]) + 0.0025 * kB[u]) + out;  // B outer, A hashed
-                const double nlB = (base + (0.0025 * kB[u]) * kA[u]) + out;
-                const bool hA = hjA <= nlA, hB = hjB <= nlB;
-                offer_if<CM>(on, best, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
-                offer_if<CM>(on, best, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
-            }
-        }
     }
-    store_best(M, off_k + rank, best, cardS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (kUnfused) sink.recs[sink.slot[r]] = PruneRec{pa[r], S[r], cardS[r]};
+        else store_best(M, off_k + pa[r], best[r], cardS[r]);
+    }
+}
+
+// Prune step of the unfused ablation: one lane per set slot of level k
+// reduces the k pair keys of its set (members without a pair hold the worst
+// key) and writes the memo entry.
+template <int CM>
+__device__ __forceinline__ void prune_sets(const MemoPtrs &M, uint32_t k, uint64_t off_k, uint32_t count,
+                                           const PairKey *keys, const PruneRec *recs, uint64_t i0, uint64_t stride) {
+    for (uint64_t i = i0; i < count; i += stride) {
+        Key best = worst_key();
+        for (uint32_t j = 0; j < k; ++j) {
+            const PairKey p = keys[i * k + j];
+            const Key o{p.c, p.l, p.op};
+            if (key_less(o, best)) best = o;
+        }
+        const PruneRec rec = recs[i];
+        store_best(M, off_k + rec.rank, best, rec.card);
+    }
+}
+
+// Alg. 2 for one connected S of a tree join graph.  With the tree rooted at
+// relation 0, removing the edge (parent(c), c) of G[S] gives the pair
+// (desc(c) & S, S minus that) for every c in S whose parent is in S, which
+// is every member but the topmost one.  When desc(c) & S = {c} the
+// complement's colex rank follows from prefix sums,
+// rank(S - s_j) = sum_{i<j} C(s_i, i+1) + sum_{i>j} C(s_i, i), and the
+// singleton's cost and card come from LDS.
+template <int CM, int kPairBatch = MPDP_TREE_PAIR_BATCH>
+__device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t bsum,
+                                              uint32_t k, uint64_t off_k, const double *__restrict__ cost_km1,
+                                              const double *__restrict__ card_km1) {
+    eval_tree_sets<CM, 1, kPairBatch>(L, M, &S, &bsum, k, off_k, cost_km1, card_km1);
 }
 
 // eval_tree_set with the pairs of S spread over a group of P lanes (P
@@ -437,8 +640,8 @@ __device__ __forceinline__ void eval_tree_set_split(const LdsGraph &L, const Mem
             pb += L.binom[m * 33 + i];
             const uint32_t r = pa + (bsum - pb);  // colex rank of S - {m} at level k - 1
             pa += L.binom[m * 33 + i + 1];
-            if ((uint32_t)(i % P) == sub && (S & L.pbit[m])) {
-                Av[i / P] = L.desc[m] & S;
+            if ((uint32_t)(i % P) == sub && (S & L.pd[m][0])) {
+                Av[i / P] = L.pd[m][1] & S;
                 rk[i / P] = r;
             }
         }
@@ -851,14 +1054,36 @@ __device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoP
 // scatter fused): it walks the ranges w0, w0 + wstride, ... (below wend) of
 // 64 * kTreeChunk colex ranks (kTreeChunk consecutive ranks per lane: unrank the
 // first, then the same-popcount successor), appends the connected sets to
-// its LDS ring in rank order and evaluates 64 of them at a time, one per
-// lane, so no lane idles on a disconnected candidate.  Returns the number of
-// connected sets it found (uniform across the wave).
-template <int CM, int kTreeChunk, bool kCompact = true>
+// its LDS ring (kRingN entries) in rank order, each with its sum of
+// C(s_i, i), and evaluates 64 * kTreeSetsPerLane of them at a time,
+// kTreeSetsPerLane per lane, so no lane idles on a disconnected candidate.
+// Returns the number of connected sets it found (uniform across the wave).
+// Outputs of the unfused-prune ablation (see TreeSink): the pair keys, the
+// set records and the counter that hands out their slots.
+struct UnfusedOut {
+    PairKey *keys;
+    PruneRec *recs;
+    uint32_t *slots;
+};
+
+// Slots for `count` sets (the lanes below count), one atomic per wave.
+__device__ __forceinline__ uint32_t take_slots(uint32_t *slots, uint32_t count, uint32_t lane) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(slots, count);
+    return (uint32_t)__shfl((int)base, 0) + lane;
+}
+
+template <int CM, int kTreeChunk, bool kCompact = true, int kRingN = kRing, int kTreeSetsPerLane = 1,
+          int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false>
 __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
                                     uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *ring,
-                                    uint32_t *ring_rank, uint32_t lane) {
-    static_assert(kRing >= 63 + 64 * kTreeChunk, "ring too small");
+                                    uint32_t *ring_bsum, uint32_t lane,
+                                    UnfusedOut uo = UnfusedOut{nullptr, nullptr, nullptr}) {
+    static_assert(kRingN >= 64 * kTreeSetsPerLane - 1 + 64 * kTreeChunk, "ring too small");
+    static_assert(!kUnfused || (kCompact && kTreeSetsPerLane == 1), "the unfused ablation is one set per lane");
+    TreeSink sink;
+    sink.keys = uo.keys;
+    sink.recs = uo.recs;
     const unsigned long long below_me = (1ull << lane) - 1ull;
     const uint64_t per_wave = 64ull * kTreeChunk;
     const uint64_t off_k = L.loff[k], off_km1 = L.loff[k - 1];
@@ -867,30 +1092,36 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
     uint32_t head = 0, tail = 0;  // ring cursors, uniform across the wave
     for (uint64_t w = w0; w < wend; w += wstride) {
         const uint64_t r0 = w * per_wave + (uint64_t)lane * kTreeChunk;
-        uint32_t S = r0 < ncand ? colex_unrank(L.binom, n, (int)k, (uint32_t)r0) : 0u;
-        uint32_t sets[kTreeChunk];
+        uint32_t b = 0;
+        uint32_t S = r0 < ncand ? colex_unrank_b(L.binom, n, (int)k, (uint32_t)r0, b) : 0u;
+        uint32_t sets[kTreeChunk], bsums[kTreeChunk];
         uint32_t keep = 0;
 #pragma unroll
         for (int j = 0; j < kTreeChunk; ++j) {
             sets[j] = S;
+            bsums[j] = b;
             if (r0 + (uint64_t)j < ncand) {
                 // G[S] is a forest whose edges are the members with their
                 // parent in S; it is one tree when there are k - 1 of them
                 if ((uint32_t)popc32(S & children(L.ch, S)) == k - 1) keep |= 1u << j;
+                b = next_bsum(S, b);
                 S = next_subset(S);
             }
         }
         const uint32_t mine = (uint32_t)popc32(keep);
+        // exclusive prefix of `mine` (at most kTreeChunk) across the wave,
+        // one ballot per bit of kTreeChunk
+        constexpr int kBits = kTreeChunk >= 8 ? 4 : (kTreeChunk >= 4 ? 3 : (kTreeChunk >= 2 ? 2 : 1));
+        static_assert(kTreeChunk < (1 << kBits), "prefix bits");
         uint32_t before = 0;
 #pragma unroll
-        for (int b = 0; b < 3; ++b)  // exclusive prefix of `mine` (<= 4) across the wave
+        for (int b = 0; b < kBits; ++b)
             before += (uint32_t)__popcll(__ballot((mine >> b) & 1u) & below_me) << b;
         const uint32_t total = (uint32_t)__shfl((int)(before + mine), 63);
         if (!kCompact) {  // ablation: each lane evaluates the sets it kept, lanes diverge
 #pragma unroll
             for (int j = 0; j < kTreeChunk; ++j)
-                if (keep & (1u << j))
-                    eval_tree_set<CM>(L, M, sets[j], (uint32_t)(r0 + j), k, off_k, cost_km1, card_km1);
+                if (keep & (1u << j)) eval_tree_set<CM, kPairBatch>(L, M, sets[j], bsums[j], k, off_k, cost_km1, card_km1);
             tail += total;
             head = tail;
             continue;
@@ -899,22 +1130,38 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
 #pragma unroll
         for (int j = 0; j < kTreeChunk; ++j)
             if (keep & (1u << j)) {
-                ring[pos % kRing] = sets[j];
-                ring_rank[pos % kRing] = (uint32_t)(r0 + j);
+                ring[pos % kRingN] = sets[j];
+                ring_bsum[pos % kRingN] = bsums[j];
                 ++pos;
             }
         tail += total;
         wave_sync_lds();
-        while (tail - head >= 64) {
-            const uint32_t s = ring[(head + lane) % kRing], r = ring_rank[(head + lane) % kRing];
-            eval_tree_set<CM>(L, M, s, r, k, off_k, cost_km1, card_km1);
-            head += 64;
+        while (tail - head >= 64u * kTreeSetsPerLane) {
+            uint32_t s[kTreeSetsPerLane], r[kTreeSetsPerLane];
+#pragma unroll
+            for (int j = 0; j < kTreeSetsPerLane; ++j) {
+                s[j] = ring[(head + 64u * j + lane) % kRingN];
+                r[j] = ring_bsum[(head + 64u * j + lane) % kRingN];
+            }
+            if (kUnfused) sink.slot[0] = take_slots(uo.slots, 64u, lane);
+            eval_tree_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused>(L, M, s, r, k, off_k, cost_km1, card_km1,
+                                                                       sink);
+            head += 64u * kTreeSetsPerLane;
         }
         wave_sync_lds();
     }
-    if (tail != head && lane < tail - head) {
-        const uint32_t s = ring[(head + lane) % kRing], r = ring_rank[(head + lane) % kRing];
-        eval_tree_set<CM>(L, M, s, r, k, off_k, cost_km1, card_km1);
+    while (tail - head >= 64) {
+        const uint32_t s = ring[(head + lane) % kRingN], r = ring_bsum[(head + lane) % kRingN];
+        if (kUnfused) sink.slot[0] = take_slots(uo.slots, 64u, lane);
+        eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+        head += 64;
+    }
+    if (tail != head) {
+        if (kUnfused) sink.slot[0] = take_slots(uo.slots, tail - head, lane);
+        if (lane < tail - head) {
+            const uint32_t s = ring[(head + lane) % kRingN], r = ring_bsum[(head + lane) % kRingN];
+            eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+        }
     }
     wave_sync_lds();
     return tail;

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "mpdp.h"
@@ -144,10 +145,10 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
             }
         }
         for (uint32_t v = 0; v < n; ++v) {
-            L.desc[v] = 1u << v;
-            L.pbit[v] = parent[v] >= 0 ? (1u << parent[v]) : 0u;
+            L.pd[v][1] = 1u << v;
+            L.pd[v][0] = parent[v] >= 0 ? (1u << parent[v]) : 0u;
         }
-        for (int i = tail - 1; i > 0; --i) L.desc[parent[order[i]]] |= L.desc[order[i]];
+        for (int i = tail - 1; i > 0; --i) L.pd[parent[order[i]]][1] |= L.pd[order[i]][1];
     }
     // selectivities of the edges (u, v), u < v, grouped by v, u ascending
     uint32_t at = 0;
@@ -166,7 +167,7 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
     // relation's row (relations beyond n have empty rows)
     uint32_t kids[32] = {0};  // tree joins: children of each relation
     if (q.is_tree)
-        for (uint32_t v = 1; v < n; ++v) kids[__builtin_ctz(L.pbit[v])] |= 1u << v;
+        for (uint32_t v = 1; v < n; ++v) kids[__builtin_ctz(L.pd[v][0])] |= 1u << v;
     for (int b = 0; b < 4; ++b) {
         L.nb[b][0] = 0;
         L.ch[b][0] = 0;
@@ -219,6 +220,29 @@ char *pinned_staging(size_t bytes) {
 // Bytes of counters, plan and root cost read back per call, as far as the
 // no-allocation path keeps them on the stack (n <= 32 needs under 3 KB).
 constexpr size_t kNoAllocDownBytes = 4096;
+
+// Device buffer of the unfused-prune ablation (measurement only), one per
+// device, grown on demand and kept for the process's lifetime.
+void *ablation_buffer(size_t bytes) {
+    static std::mutex mu;
+    static void *buf[64] = {nullptr};
+    static size_t cap[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cap[dev] < bytes) {
+        if (buf[dev]) (void)hipFree(buf[dev]);
+        buf[dev] = nullptr;
+        cap[dev] = 0;
+        if (hipMalloc(&buf[dev], bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            buf[dev] = nullptr;
+            return nullptr;
+        }
+        cap[dev] = bytes;
+    }
+    return buf[dev];
+}
 
 struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -279,6 +303,23 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
     }
     HIPCHK(mpdp::launch_init(dg, n, memo, cnt, s));
     const bool general = force_general || !q.is_tree;
+    // unfused-prune ablation (tree joins): room for every pair key and set
+    // record of the widest level
+    const bool unfused = !general && (flags & MPDP_FLAG_ABLATE_UNFUSED_PRUNE) != 0;
+    mpdp::PairKey *ukeys = nullptr;
+    mpdp::PruneRec *urecs = nullptr;
+    if (unfused) {
+        uint64_t most_keys = 0, most_sets = 0;
+        for (uint32_t k = 2; k <= n; ++k) {
+            most_keys = std::max<uint64_t>(most_keys, binom64(n, k) * k);
+            most_sets = std::max<uint64_t>(most_sets, binom64(n, k));
+        }
+        const size_t kb = align_up(sizeof(mpdp::PairKey) * most_keys);
+        char *ab = static_cast<char *>(ablation_buffer(kb + sizeof(mpdp::PruneRec) * most_sets));
+        if (!ab) return MPDP_ENOMEM;
+        ukeys = reinterpret_cast<mpdp::PairKey *>(ab);
+        urecs = reinterpret_cast<mpdp::PruneRec *>(ab + kb);
+    }
     uint64_t candidates = 0;
     uint32_t launches = 0;
     for (uint32_t k = 2; k <= n; ++k) {
@@ -289,6 +330,8 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         if (timing) HIPCHK(hipEventRecord(ev.ev[4 * k - 7], s));
         if (general)
             HIPCHK(mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, heavy, cnt, memo, s));
+        else if (unfused)  // ablation: evaluate writes every pair's key, prune reduces
+            HIPCHK(mpdp::launch_level_tree_unfused(dg, q.cost_model, k, nc, cnt, memo, ukeys, urecs, s));
         else  // tree joins: unrank, filter and evaluate in one kernel per level
             HIPCHK(mpdp::launch_level_tree(dg, q.cost_model, k, nc, (flags & MPDP_FLAG_ABLATE_NO_COMPACTION) == 0, cnt,
                                            memo, s));

@@ -27,8 +27,8 @@ struct LdsImage {
     uint32_t ch[4][256];                      // tree joins rooted at 0: children of a set, per byte
     uint32_t lo[kMaxRel][2];                  // per v: bit of its lowest neighbour u < v (0 without one), its other neighbours u < v
     uint32_t adj[kMaxRel];                    // bit u of adj[v]: edge (u, v)
-    uint32_t pbit[kMaxRel];                   // tree joins rooted at 0: bit of the parent, 0 at the root
-    uint32_t desc[kMaxRel];                   // tree joins: relations of the subtree rooted at v
+    uint32_t pd[kMaxRel][2];                  // tree joins rooted at 0, per v: bit of its parent (0 at the root),
+                                              // then the relations of the subtree rooted at v
     uint32_t selrow[kMaxRel];                 // first sel entry of relation v
     uint32_t binom[33 * 33];                  // C(a, b) at [a * 33 + b]
     uint32_t pad[3];
@@ -37,6 +37,7 @@ struct LdsImage {
 };
 static_assert(offsetof(LdsImage, csel) % 16 == 0, "(card, sel) pairs are read as 16-byte units");
 static_assert(offsetof(LdsImage, lo) % 8 == 0, "lowest-neighbour pairs are read as 8-byte units");
+static_assert(offsetof(LdsImage, pd) % 8 == 0, "(parent, subtree) pairs are read as 8-byte units");
 static_assert(offsetof(LdsImage, sel) % 16 == 0, "the tree prefix ends on a 16-byte boundary");
 constexpr size_t kTreeLdsBytes = offsetof(LdsImage, sel) + 8 * 32;  // the prefix plus 32 selectivities
 static_assert(sizeof(LdsImage) % 16 == 0, "LdsImage is copied in 16-byte units");
@@ -64,6 +65,7 @@ struct Counters {
     uint32_t level_count[34];   // connected sets found at each level (block-based path: those inducing a tree)
     uint32_t general_count[34]; // block-based path: the other connected sets of each level
     uint32_t heavy_count[34];   // sets handed to the heavy kernel at each level
+    uint32_t prune_slots[34];   // unfused-prune ablation: sets whose pair keys were written at each level
     uint32_t extract_error;     // nonzero if plan extraction met an inconsistent memo
     uint32_t pad;
     unsigned long long evaluated; // Alg. 3 candidates (general path)
@@ -134,6 +136,22 @@ constexpr uint32_t kAblateDpsub = 1u;
 
 hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, Counters *cnt,
                              MemoPtrs memo, hipStream_t s);
+
+// Unfused-prune ablation of a tree level (measurement only): the evaluate
+// kernel writes the key of every pair of every connected set (16 bytes,
+// k per set, slot-major) and the set's record, a separate prune kernel
+// reduces each set's keys and writes its memo entry.  pair_keys holds at
+// least C(n, k) * k keys, set_recs C(n, k) records.
+struct PruneRec {
+    uint32_t rank, set;
+    double card;
+};
+struct PairKey {
+    unsigned long long c;
+    uint32_t l, op;
+};
+hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
+                                     MemoPtrs memo, PairKey *pair_keys, PruneRec *set_recs, hipStream_t s);
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
                                const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, hipStream_t s);
 hipError_t launch_extract(const DevGraph *g, uint32_t n, MemoPtrs memo, mpdp_plan_node *plan,

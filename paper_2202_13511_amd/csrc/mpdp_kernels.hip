@@ -68,17 +68,46 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     // the LDS image up to the first 32 selectivities: a tree join reads no
     // more (n - 1 <= 31 edges, and no neighbour tables)
     __shared__ __align__(16) unsigned char lds_tree[kTreeLdsBytes];
-    __shared__ uint32_t ring_all[kWaves][kRing];
-    __shared__ uint32_t ring_rank_all[kWaves][kRing];
+    __shared__ uint32_t ring_all[kWaves][kTreeRing];
+    __shared__ uint32_t ring_bsum_all[kWaves][kTreeRing];
     stage_graph_prefix(g, lds_tree, kTreeLdsBytes);
     const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t per_wave = 64ull * kTreeChunk;
     uint64_t w0, ws, we;
     wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
-    const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact>(
-        L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_rank_all[threadIdx.x >> 6], lane);
+    const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact, kTreeRing, tree_sets_per_lane<CM>()>(
+        L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_bsum_all[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
+}
+
+// Unfused-prune ablation of a tree level (measurement only): the same walk
+// and pair costs, but every pair's key is written out (Section 5 before the
+// fusion of prune into evaluate) for k_prune.
+template <int CM, int kTreeChunk>
+__global__ __launch_bounds__(kBlock) void k_level_tree_unfused(const DevGraph *g, uint32_t k, uint64_t ncand,
+                                                               Counters *cnt, MemoPtrs M, PairKey *keys,
+                                                               PruneRec *recs) {
+    __shared__ __align__(16) unsigned char lds_tree[kTreeLdsBytes];
+    __shared__ uint32_t ring_all[kWaves][kTreeRing];
+    __shared__ uint32_t ring_bsum_all[kWaves][kTreeRing];
+    stage_graph_prefix(g, lds_tree, kTreeLdsBytes);
+    const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t per_wave = 64ull * kTreeChunk;
+    uint64_t w0, ws, we;
+    wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
+    const uint32_t found = level_tree_wave<CM, kTreeChunk, true, kTreeRing, 1, MPDP_TREE_PAIR_BATCH, true>(
+        L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_bsum_all[threadIdx.x >> 6], lane,
+        UnfusedOut{keys, recs, &cnt->prune_slots[k]});
+    if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
+}
+
+// Prune of the unfused ablation: one thread per set slot of level k.
+__global__ __launch_bounds__(kBlock) void k_prune(const DevGraph *g, uint32_t k, const Counters *cnt, MemoPtrs M,
+                                                  const PairKey *keys, const PruneRec *recs) {
+    prune_sets<0>(M, k, g->lds.loff[k], cnt->prune_slots[k], keys, recs,
+                  (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
 }
 
 // A small level of a tree join graph (few candidates, many members per set):
@@ -239,7 +268,11 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
                                memo);
         return hipGetLastError();
     }
-    const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
+    // eight ranks per lane only under C_out: PG-like keeps more registers
+    // per set live and measured slower with them
+    const int chunk = (cost_model == MPDP_COST_COUT && ncand >= 64ull * 8 * kWantWaves)
+                          ? 8
+                          : (ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1));
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
@@ -251,7 +284,8 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
             hipLaunchKernelGGL((k_level_tree<CMV, CH, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
     } while (0)
     if (cost_model == MPDP_COST_COUT) {
-        if (chunk == 4) MPDP_LEVEL_TREE(MPDP_COST_COUT, 4);
+        if (chunk == 8) MPDP_LEVEL_TREE(MPDP_COST_COUT, 8);
+        else if (chunk == 4) MPDP_LEVEL_TREE(MPDP_COST_COUT, 4);
         else if (chunk == 2) MPDP_LEVEL_TREE(MPDP_COST_COUT, 2);
         else MPDP_LEVEL_TREE(MPDP_COST_COUT, 1);
     } else {
@@ -260,6 +294,32 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
         else MPDP_LEVEL_TREE(MPDP_COST_PGLIKE, 1);
     }
 #undef MPDP_LEVEL_TREE
+    return hipGetLastError();
+}
+
+hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
+                                     MemoPtrs memo, PairKey *keys, PruneRec *recs, hipStream_t s) {
+    // the launch shape of the fused kernel on the same level (chunk and grid)
+    constexpr uint64_t kWantWaves = 1024;
+    const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
+    const uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
+    const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
+    const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
+#define MPDP_UNFUSED(CMV, CH) \
+    hipLaunchKernelGGL((k_level_tree_unfused<CMV, CH>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo, keys, recs)
+    if (cost_model == MPDP_COST_COUT) {
+        if (chunk == 4) MPDP_UNFUSED(MPDP_COST_COUT, 4);
+        else if (chunk == 2) MPDP_UNFUSED(MPDP_COST_COUT, 2);
+        else MPDP_UNFUSED(MPDP_COST_COUT, 1);
+    } else {
+        if (chunk == 4) MPDP_UNFUSED(MPDP_COST_PGLIKE, 4);
+        else if (chunk == 2) MPDP_UNFUSED(MPDP_COST_PGLIKE, 2);
+        else MPDP_UNFUSED(MPDP_COST_PGLIKE, 1);
+    }
+#undef MPDP_UNFUSED
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prune, dim3(grid_for(ncand, kBlock)), dim3(kBlock), 0, s, g, k, cnt, memo, keys, recs);
     return hipGetLastError();
 }
 

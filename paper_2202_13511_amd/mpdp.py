@@ -21,7 +21,7 @@ MPDP_OK, MPDP_EINVAL, MPDP_ENOTCONNECTED, MPDP_ETOOLARGE, MPDP_ENOMEM, MPDP_EDEV
 MPDP_COST_COUT, MPDP_COST_PGLIKE = 0, 1
 MPDP_OP_SCAN, MPDP_OP_HASH, MPDP_OP_NESTLOOP, MPDP_OP_JOIN = 0, 1, 2, 3
 MPDP_FLAG_TIMING = 1
-MPDP_FLAG_ABLATE_DPSUB, MPDP_FLAG_ABLATE_NO_COMPACTION = 2, 4
+MPDP_FLAG_ABLATE_DPSUB, MPDP_FLAG_ABLATE_NO_COMPACTION, MPDP_FLAG_ABLATE_UNFUSED_PRUNE = 2, 4, 8
 _FLAG_FORCE_GENERAL = 0x100   # test aid: block-based kernel on tree joins too
 _FLAG_BATCH_ALL_TEAMS = 0x200  # test aid: every batched query that may take a team of workgroups takes one
 

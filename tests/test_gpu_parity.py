@@ -89,9 +89,10 @@ def test_block_kernel_on_trees(cm):
 @pytest.mark.parametrize("cm", CMS)
 def test_ablations_leave_results_unchanged(cm):
     """The measurement-only ablations (DPSUB's vertex-based candidates on the
-    GPU; the tree kernel without LDS compaction) reach the oracle's memo bit
-    for bit; DPSUB evaluates 2^|S| - 2 candidates per connected set (the
-    oracle's DPSUB also counts the empty and the full subset)."""
+    GPU; the tree kernel without LDS compaction; prune not fused into
+    evaluate) reach the oracle's memo bit for bit; DPSUB evaluates 2^|S| - 2
+    candidates per connected set (the oracle's DPSUB also counts the empty
+    and the full subset)."""
     for q in [W.star(11, 4), W.snowflake(14, 5), W.cycle_chords(2, n=11, chords=3), W.clique(8, 1),
               W.random_connected(11, 3, 0.3)]:
         ref = oracle.mpdp(q, cm)
@@ -102,9 +103,11 @@ def test_ablations_leave_results_unchanged(cm):
         assert res.stats["evaluated_pairs"] == d.evaluated - 2 * d.connected_sets, q.name
         assert 2 * res.stats["ccp_pairs"] == ref.ccp_ordered, q.name
         if q.m == q.n - 1:
-            res, gm = run_ws(q, cm, flags=mpdp.MPDP_FLAG_ABLATE_NO_COMPACTION)
-            check_memo(q, gm, ref)
-            check_plan(q, res, ref)
+            for flag in (mpdp.MPDP_FLAG_ABLATE_NO_COMPACTION, mpdp.MPDP_FLAG_ABLATE_UNFUSED_PRUNE):
+                res, gm = run_ws(q, cm, flags=flag)
+                check_memo(q, gm, ref)
+                check_plan(q, res, ref)
+                assert 2 * res.stats["ccp_pairs"] == ref.ccp_ordered, q.name
 
 
 def test_self_allocating_entry_point():
