@@ -145,3 +145,26 @@ def test_widest_bitmap_chain32(cm):
         c, k, L, op = ref[S]
         assert nd["cost"] == c and nd["card"] == k and res.plan[nd["left"]]["relset"] == L
     assert res.stats["connected_sets"] == 32 * 33 // 2 - 32
+
+
+def test_recorded_sequence_replays():
+    """Queries of up to 20 relations replay a launch sequence recorded once
+    per workspace and shape: replays with new data, interleaved with other
+    shapes, eager torch work and synchronizations, each match the oracle."""
+    import torch
+    ws = {n: mpdp.workspace(n, 1, "cuda") for n in (12, 14)}
+    refs = {}
+    for rnd in range(4):
+        for cm in (mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE):
+            for q in (W.star(12, rnd), W.snowflake(14, rnd), W.cycle_chords(rnd, n=12, chords=3),
+                      W.random_connected(14, rnd, 0.3)):
+                key = (q.name, cm)
+                if key not in refs:
+                    refs[key] = oracle.mpdp(q, cm)
+                ref = refs[key]
+                res = mpdp.mpdp_optimize_ws(q, cm, ws[q.n])
+                check_plan(q, res, ref)
+                assert res.stats["connected_sets"] == ref.connected_sets, q.name
+                x = torch.arange(1000, device="cuda", dtype=torch.float32).sum()
+                torch.cuda.synchronize()
+                assert float(x) == 499500.0
