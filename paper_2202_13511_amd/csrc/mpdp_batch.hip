@@ -27,6 +27,8 @@ constexpr int kBW = kBatchBlock / 64;
 // members per gather batch of a tree set: three keeps the kernel (every
 // path of a query inlined, 128 registers per lane) from spilling far more
 constexpr int kBatchPairBatch = 3;
+// (for the same reason Alg. 3's candidate chunks take the plain subset walk
+// here, without the per-chunk neighbourhood tables)
 constexpr unsigned long long kTeamWaitTicks = 200000000ull;  // 2 s of the 100 MHz device clock
 
 // The workgroups of a team meet here for the `phase`-th time.  Every wave
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
             const uint32_t ngen = team ? load_shared_count(&R->ngen[k]) : s_ngen[k];
             const uint32_t count = ntree + ngen;
             // light work: tree-inducing sets one per lane, other sets one per wave
-            light_sets<CM>(L, M, lists + (k & 1u) * cap, cap, ntree, ngen, w0, wstride, WS[wave], hv, nhp, lane,
+            light_sets<CM, false>(L, M, lists + (k & 1u) * cap, cap, ntree, ngen, w0, wstride, WS[wave], hv, nhp, lane,
                            my_ccp, my_eval, false, (Q.sched >> kSchedHeavyShift) & 0xffffu);
             if (k < n) filter_level(k + 1);
             if (team) {
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 
                 const SetBlocks sb = hsb;
                 const double cardS = card_of_wave(L, S, threadIdx.x & 63u);
                 Key best = worst_key();
-                eval_chunks<CM>(L, M, WS[0], S, sb, t, blockDim.x, cardS, best, my_ccp);
+                eval_chunks<CM, false>(L, M, WS[0], S, sb, t, blockDim.x, cardS, best, my_ccp);
                 best = wave_min(best);
                 if (lane == 0) hkeys[wave] = best;
                 __syncthreads();

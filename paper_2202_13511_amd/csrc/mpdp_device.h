@@ -943,7 +943,7 @@ __device__ __forceinline__ void split_ranks(const LdsGraph &L, uint32_t S, uint3
 // each unordered pair is met once and both orientations are costed) the CCP
 // check is that G[lb] and G[rb] are connected (they are adjacent because the
 // block is); then S_left = grow(lb, S - rb) and S_right = S - S_left.
-template <int CM>
+template <int CM, bool kChunkTables = true>
 __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M, const WaveScratch &W, uint32_t S,
                                             const SetBlocks &sb, uint32_t first, uint32_t stride, double cardS,
                                             Key &best, unsigned long long &ccp) {
@@ -958,6 +958,59 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
         const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
         const uint32_t j0 = (ch - W.cpre[bi]) << sb.shift;
         const uint32_t j1 = min(j0 + (1u << sb.shift), hb);
+        if (kChunkTables && !full && sb.shift == 4 && popc32(rest) >= 5) {
+            // 16 candidates share the members of rest above its lowest four
+            // (`hi` in lb, the others of that part in rb) and differ in
+            // which of those four (low4) they take.  The neighbourhoods of
+            // the shared parts are looked up once per chunk and those of
+            // the 16 low combinations built from four adjacency rows, so
+            // the isolated-member test is a few register operations per
+            // candidate; survivors take the breadth-first checks.
+            const uint32_t m0 = lowbit(rest), r1 = rest ^ m0, m1 = lowbit(r1), r2 = r1 ^ m1, m2 = lowbit(r2),
+                           r3 = r2 ^ m2, m3 = lowbit(r3), low4 = m0 | m1 | m2 | m3;
+            const uint32_t a0 = L.adj[ctz32(m0)], a1 = L.adj[ctz32(m1)], a2 = L.adj[ctz32(m2)],
+                           a3 = L.adj[ctz32(m3)];
+            const uint32_t hi = deposit(j0, rest);             // j0 is a multiple of 16
+            const uint32_t H = lo | hi, RH = (rest & ~low4) & ~hi;
+            const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH), N4 = a0 | a1 | a2 | a3;
+            // the whole chunk is dead when a shared member on either side
+            // has no neighbour among its side's shared members and low4
+            // (that side then has two or more members in every candidate)
+            if (((H & (H - 1)) && (H & ~(NH | N4))) || ((RH & (RH - 1)) && (RH & ~(NRH | N4)))) continue;
+            // pass 1 (unrolled, registers only): which candidates survive;
+            // candidate t takes the members of low4 named by the bits of t
+            // (a compile-time choice, so each side's set and neighbourhood
+            // is at most three ORs of the four members and rows)
+            uint32_t live = 0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const uint32_t ls = ((t & 1) ? m0 : 0u) | ((t & 2) ? m1 : 0u) | ((t & 4) ? m2 : 0u) |
+                                    ((t & 8) ? m3 : 0u);
+                const uint32_t nl = ((t & 1) ? a0 : 0u) | ((t & 2) ? a1 : 0u) | ((t & 4) ? a2 : 0u) |
+                                    ((t & 8) ? a3 : 0u);
+                const uint32_t nr = ((t & 1) ? 0u : a0) | ((t & 2) ? 0u : a1) | ((t & 4) ? 0u : a2) |
+                                    ((t & 8) ? 0u : a3);
+                const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
+                const bool dead = ((lb & (lb - 1)) && (lb & ~(NH | nl))) || ((rb & (rb - 1)) && (rb & ~(NRH | nr)));
+                live |= (!dead && j0 + (uint32_t)t < j1) ? (1u << t) : 0u;
+            }
+            // pass 2: the survivors' breadth-first checks and costs
+            for (uint32_t Lm = live; Lm; Lm &= Lm - 1) {
+                const uint32_t t = (uint32_t)ctz32(Lm);
+                const uint32_t ls = ((t & 1u) ? m0 : 0u) | ((t & 2u) ? m1 : 0u) | ((t & 4u) ? m2 : 0u) |
+                                    ((t & 8u) ? m3 : 0u);
+                const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
+                if (grow(L.nb, lo, lb) != lb) continue;
+                if (grow(L.nb, lowbit(rb), rb) != rb) continue;
+                ++ccp;
+                const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
+                uint32_t rl, rr;
+                split_ranks(L, S, Sl, rl, rr);
+                const int kl = popc32(Sl);
+                eval_pair<CM>(M, Sl, S ^ Sl, L.loff[kl] + rl, L.loff[k - kl] + rr, cardS, best);
+            }
+            continue;
+        }
         uint32_t sub = deposit(j0, rest);
         for (uint32_t j = j0; j < j1; ++j) {
             const uint32_t lb = lo | sub, rb = b ^ lb;
@@ -1253,7 +1306,7 @@ __device__ void filter_wave(const LdsGraph &L, int n, uint32_t k, uint64_t ncand
 // groups, one other set from the back of `list`, taken by the whole wave
 // (Alg. 3 over its blocks).  A set with more than kHeavyChunks 16-candidate
 // chunks is appended to `heavy` for a whole workgroup instead.
-template <int CM>
+template <int CM, bool kChunkTables = true>
 __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *list, uint32_t cap, uint32_t ntree,
                            uint32_t ngen, uint32_t w0, uint32_t wstride, WaveScratch &W, uint32_t *heavy,
                            uint32_t *nheavy, uint32_t lane, unsigned long long &ccp, unsigned long long &evaluated,
@@ -1280,7 +1333,7 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
         wave_sync_lds();
         const double cardS = card_of_wave(L, S, lane);
         Key best = worst_key();
-        eval_chunks<CM>(L, M, W, S, sb, lane, 64u, cardS, best, ccp);
+        eval_chunks<CM, kChunkTables>(L, M, W, S, sb, lane, 64u, cardS, best, ccp);
         best = wave_min(best);
         const uint64_t at = memo_index_wave(L, S, lane);
         if (lane == 0) store_best(M, at, best, cardS);
