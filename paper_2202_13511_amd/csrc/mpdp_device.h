@@ -34,7 +34,10 @@ constexpr uint32_t kPersistGridCout = MPDP_TREE_GRID_COUT;
 constexpr int kTreeSplitLanes = 8;
 constexpr uint32_t kTreeSplitMinK = 8;
 constexpr uint64_t kTreeSplitMaxCand = 4096;
-constexpr uint32_t kHeavyChunks = 256;   // above this many 16-candidate chunks a set is heavy
+#ifndef MPDP_HEAVY_CHUNKS
+#define MPDP_HEAVY_CHUNKS 512
+#endif
+constexpr uint32_t kHeavyChunks = MPDP_HEAVY_CHUNKS;   // above this many 16-candidate chunks a set is heavy
 constexpr int kHeavyBlock = 1024;        // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
 
@@ -806,7 +809,9 @@ struct SetBlocks {
     uint32_t A;             // cut vertices of G[S]
     uint32_t total_chunks;  // candidate chunks over all blocks, 2^shift candidates each
     uint32_t shift;
-    uint32_t chunks16;      // chunks at 16 candidates each (decides light or heavy)
+    uint32_t chunks16;      // chunks at 16 candidates each (decides light or heavy in the batched kernel)
+    uint32_t work16;        // the same with a sparse block's chunks weighted 1/16: most of its
+                            // candidates fall to the per-chunk neighbourhood test (per-level kernels)
     unsigned long long evaluated;  // Alg. 3 candidates of S: sum over blocks of 2^b - 2
 };
 
@@ -840,7 +845,7 @@ __device__ SetBlocks whole_set(uint32_t S, WaveScratch &W, int lane, uint32_t bu
         W.cpre[0] = 0;
         W.cpre[1] = chunks;
     }
-    return SetBlocks{0u, chunks, shift, (half + 15u) >> 4, (1ull << k) - 2ull};
+    return SetBlocks{0u, chunks, shift, (half + 15u) >> 4, (half + 15u) >> 4, (1ull << k) - 2ull};
 }
 
 __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, int lane, uint32_t budget) {
@@ -902,7 +907,7 @@ __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, 
         const int bs = popc32(myblk);
         if (top && bs > 3) complete = d2 == (uint32_t)(bs * (bs - 1));
     }
-    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, w4 = 0;
     for (uint32_t U = T; U; U &= U - 1) {
         const uint32_t h = rdlane(half, ctz32(U));
         c0 += h;
@@ -910,6 +915,7 @@ __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, 
         c2 += (h + 3u) >> 2;
         c3 += (h + 7u) >> 3;
         c4 += (h + 15u) >> 4;
+        w4 += rdlane(complete, ctz32(U)) ? (h + 15u) >> 4 : (h + 255u) >> 8;
     }
     const uint32_t shift = c0 <= budget ? 0u : c1 <= budget ? 1u : c2 <= budget ? 2u : c3 <= budget ? 3u : 4u;
     const uint32_t round = (1u << shift) - 1u;
@@ -922,7 +928,7 @@ __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, 
         evaluated += (1ull << popc32(rdlane(myblk, t))) - 2ull;
     }
     if (lane == 0) W.cpre[idx] = acc;
-    return SetBlocks{A, acc, shift, c4, evaluated};
+    return SetBlocks{A, acc, shift, c4, w4, evaluated};
 }
 
 // Colex ranks of Sl and of S - Sl in one pass over the members of S.
@@ -1324,7 +1330,7 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
         }
         const uint32_t S = list[cap - 1u - (i - groups)];
         const SetBlocks sb = dpsub ? whole_set(S, W, (int)lane, 64u) : analyze_set(L, S, W, (int)lane, 64u);
-        if (sb.chunks16 > heavy_chunks) {
+        if ((kChunkTables ? sb.work16 : sb.chunks16) > heavy_chunks) {
             if (lane == 0) heavy[atomicAdd(nheavy, 1u)] = S;
             wave_sync_lds();
             continue;

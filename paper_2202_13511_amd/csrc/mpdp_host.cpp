@@ -33,7 +33,7 @@ uint64_t binom64(uint32_t a, uint32_t b) {
 }
 
 struct Layout {
-    size_t cost, card, left, op, list, heavy, graph, counters, plan, root, total;
+    size_t cost, card, left, op, list, heavy, parts, graph, counters, plan, root, total;
 };
 
 Layout make_layout(uint32_t n) {
@@ -46,6 +46,7 @@ Layout make_layout(uint32_t n) {
     L.op = o;       o = align_up(o + N);
     L.list = o;     o = align_up(o + 4 * binom64(n, n / 2));
     L.heavy = o;    o = align_up(o + 4 * binom64(n, n / 2));
+    L.parts = o;    o = align_up(o + sizeof(mpdp::HeavyPart) * mpdp::kHeavyGrid);
     L.graph = o;    o = align_up(o + sizeof(DevGraph));
     L.counters = o; o = align_up(o + sizeof(Counters));
     L.plan = o;     o = align_up(o + sizeof(mpdp_plan_node) * 64);
@@ -350,6 +351,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
                   reinterpret_cast<uint32_t *>(base + L.left), reinterpret_cast<uint8_t *>(base + L.op)};
     uint32_t *list = reinterpret_cast<uint32_t *>(base + L.list);
     uint32_t *heavy = reinterpret_cast<uint32_t *>(base + L.heavy);
+    mpdp::HeavyPart *parts = reinterpret_cast<mpdp::HeavyPart *>(base + L.parts);
     DevGraph *dg = reinterpret_cast<DevGraph *>(base + L.graph);
     Counters *cnt = reinterpret_cast<Counters *>(base + L.counters);
     mpdp_plan_node *dplan = reinterpret_cast<mpdp_plan_node *>(base + L.plan);
@@ -407,7 +409,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
             if (e == hipSuccess && timing) e = hipEventRecord(ev.ev[4 * k - 7], st);
             if (e != hipSuccess) break;
             if (general)
-                e = mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, heavy, cnt, memo, st);
+                e = mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, heavy, cnt, memo, parts, st);
             else if (unfused)  // ablation: evaluate writes every pair's key, prune reduces
                 e = mpdp::launch_level_tree_unfused(dg, q.cost_model, k, nc, cnt, memo, ukeys, urecs, st);
             else  // tree joins: unrank, filter and evaluate in one kernel per level

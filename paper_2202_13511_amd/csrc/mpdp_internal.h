@@ -152,8 +152,24 @@ struct PairKey {
 };
 hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
                                      MemoPtrs memo, PairKey *pair_keys, PruneRec *set_recs, hipStream_t s);
+// Key and card of one part of a heavy set split over several workgroups.
+struct HeavyPart {
+    unsigned long long c;
+    uint32_t l, op;
+    double card;
+    double pad;
+};
+constexpr uint32_t kHeavyGrid = 512;  // workgroups of the heavy-set kernel (two per CU)
+
+// Workgroups per heavy set: one while a level has at least one heavy set
+// per workgroup, else as many as share the grid evenly.
+__host__ __device__ inline uint32_t heavy_parts(uint32_t count, uint32_t grid) {
+    return (count == 0 || count >= grid) ? 1u : grid / count;
+}
+
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
-                               const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, hipStream_t s);
+                               const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, HeavyPart *parts,
+                               hipStream_t s);
 hipError_t launch_extract(const DevGraph *g, uint32_t n, MemoPtrs memo, mpdp_plan_node *plan,
                           double *root_cost, Counters *cnt, hipStream_t s);
 

@@ -168,33 +168,40 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
     }
 }
 
-// Alg. 3, heavy sets: one 1024-thread workgroup per set.  Wave 0 finds the
-// blocks, all 16 waves share the candidate chunks, and the plan keys are
-// reduced through LDS.
+// Alg. 3, heavy sets: one 1024-thread workgroup per set, or, when a level
+// has fewer heavy sets than workgroups (the top levels of a large cyclic
+// query: one set of all relations, then n, ...), `parts` workgroups per
+// set, each taking every parts-th run of 1024 candidate chunks; their keys
+// then go to HeavyPart records for k_heavy_reduce.  Wave 0 of each
+// workgroup finds the blocks, all 16 waves share the candidate chunks, and
+// the plan keys are reduced through LDS.
 template <int CM>
 __global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, uint32_t k, const uint32_t *heavy,
-                                                            Counters *cnt, MemoPtrs M) {
+                                                            Counters *cnt, MemoPtrs M, HeavyPart *partrec) {
     constexpr int kHW = kHeavyBlock / 64;
     __shared__ __align__(16) LdsGraph L;
     __shared__ WaveScratch W;
     __shared__ SetBlocks sbs;
     __shared__ Key keys[kHW];
+    const uint32_t count = cnt->heavy_count[k];
+    const uint32_t parts = heavy_parts(count, gridDim.x);
+    if (blockIdx.x >= count * parts) return;  // the whole workgroup, before any barrier
     stage_graph(g, L);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t count = cnt->heavy_count[k];
     unsigned long long my_ccp = 0, my_eval = 0;
-    for (uint32_t h = blockIdx.x; h < count; h += gridDim.x) {
+    for (uint32_t t = blockIdx.x; t < count * parts; t += gridDim.x) {
+        const uint32_t h = t / parts, part = t - h * parts;
         const uint32_t S = heavy[h];
         if (wave == 0) {
             const SetBlocks sb = (g->ablate & kAblateDpsub) ? whole_set(S, W, lane, kHeavyBlock)
                                                             : analyze_set(L, S, W, lane, kHeavyBlock);
-            if (lane == 0) { sbs = sb; my_eval += sb.evaluated; }
+            if (lane == 0) { sbs = sb; if (part == 0) my_eval += sb.evaluated; }
         }
         __syncthreads();
         const SetBlocks sb = sbs;
         const double cardS = card_of_wave(L, S, threadIdx.x & 63u);
         Key best = worst_key();
-        eval_chunks<CM>(L, M, W, S, sb, threadIdx.x, kHeavyBlock, cardS, best, my_ccp);
+        eval_chunks<CM>(L, M, W, S, sb, part * kHeavyBlock + threadIdx.x, parts * kHeavyBlock, cardS, best, my_ccp);
         best = wave_min(best);
         if (lane == 0) keys[wave] = best;
         __syncthreads();
@@ -202,7 +209,8 @@ __global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, u
             Key b = keys[0];
             for (int i = 1; i < kHW; ++i)
                 if (key_less(keys[i], b)) b = keys[i];
-            store_best(M, memo_index(L, S), b, cardS);
+            if (parts == 1) store_best(M, memo_index(L, S), b, cardS);
+            else partrec[t] = HeavyPart{b.c, b.l, b.op, cardS};
         }
         __syncthreads();
     }
@@ -213,6 +221,26 @@ __global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, u
     if (lane == 0 && (my_ccp || my_eval)) {
         atomicAdd(&cnt->ccp, my_ccp);
         atomicAdd(&cnt->evaluated, my_eval);
+    }
+}
+
+// The keys of a set split over several heavy workgroups: one thread per
+// set combines its parts and writes the memo entry (nothing to do when
+// every heavy set had a workgroup of its own).
+__global__ __launch_bounds__(64) void k_heavy_reduce(const DevGraph *g, uint32_t k, const uint32_t *heavy,
+                                                     const Counters *cnt, MemoPtrs M, const HeavyPart *partrec,
+                                                     uint32_t grid) {
+    const uint32_t count = cnt->heavy_count[k];
+    const uint32_t parts = heavy_parts(count, grid);
+    if (parts == 1) return;
+    for (uint32_t h = threadIdx.x; h < count; h += blockDim.x) {
+        Key b = worst_key();
+        for (uint32_t p = 0; p < parts; ++p) {
+            const HeavyPart r = partrec[h * parts + p];
+            const Key o{r.c, r.l, r.op};
+            if (key_less(o, b)) b = o;
+        }
+        store_best(M, memo_index(g->lds, heavy[h]), b, partrec[h * parts].card);
     }
 }
 
@@ -324,7 +352,8 @@ hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t
 }
 
 hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand,
-                               const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, hipStream_t s) {
+                               const uint32_t *list, uint32_t *heavy, Counters *cnt, MemoPtrs memo, HeavyPart *parts,
+                               hipStream_t s) {
     const uint32_t grid = grid_for(ncand, kWaves);
     if (cost_model == MPDP_COST_COUT)
         hipLaunchKernelGGL(k_eval_general<MPDP_COST_COUT>, dim3(grid), dim3(kBlock), 0, s, g, k, list, heavy, cnt,
@@ -334,14 +363,18 @@ hipError_t launch_eval_general(const DevGraph *g, int cost_model, uint32_t k, ui
                            memo);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // heavy sets: at most one per workgroup at a time, two workgroups per CU
-    const uint64_t hgrid64 = ncand < 512 ? (ncand ? ncand : 1) : 512;
-    const uint32_t hgrid = (uint32_t)hgrid64;
+    // heavy sets: one per workgroup at a time, two workgroups per CU; a
+    // level with fewer heavy sets than workgroups splits each over several
+    const uint32_t hgrid = kHeavyGrid;
     if (cost_model == MPDP_COST_COUT)
-        hipLaunchKernelGGL(k_eval_heavy<MPDP_COST_COUT>, dim3(hgrid), dim3(kHeavyBlock), 0, s, g, k, heavy, cnt, memo);
+        hipLaunchKernelGGL(k_eval_heavy<MPDP_COST_COUT>, dim3(hgrid), dim3(kHeavyBlock), 0, s, g, k, heavy, cnt, memo,
+                           parts);
     else
         hipLaunchKernelGGL(k_eval_heavy<MPDP_COST_PGLIKE>, dim3(hgrid), dim3(kHeavyBlock), 0, s, g, k, heavy, cnt,
-                           memo);
+                           memo, parts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_heavy_reduce, dim3(1), dim3(64), 0, s, g, k, heavy, cnt, memo, parts, hgrid);
     return hipGetLastError();
 }
 
