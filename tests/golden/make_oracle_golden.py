@@ -131,12 +131,14 @@ def one(spec, threads=1):
     rng = np.random.Generator(np.random.PCG64(1000 + seed))
     pick = np.sort(rng.choice(conn, size=min(SAMPLES, conn.size), replace=False))
     samples = [[int(S), hexbits(m.cost[S]), hexbits(m.card[S]), int(m.left[S]), int(m.op[S])] for S in pick]
-    return {
+    out = {
         "kind": kind, "n": q.n, "seed": seed, "cost_model": cm, "name": q.name, "m": q.m,
         "root_cost": hexbits(m.root_cost), "joins": joins,
         "connected_sets": m.connected_sets, "ccp_pairs": m.ccp_ordered // 2, "evaluated_pairs": evaluated,
         "samples": samples,
     }
+    del m, mask, conn  # a 30-relation memo is 22.5 GB: free it before the next query
+    return out
 
 
 ABOUT = ("Expected results of the CPU oracle (oracle.mpdp) on the full-size workloads; written by "
