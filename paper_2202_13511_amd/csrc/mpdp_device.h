@@ -955,14 +955,32 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
                                             Key &best, unsigned long long &ccp) {
     const int k = popc32(S);
     const uint32_t A = sb.A;
+    // The chunk's first candidate, deposited over the block's members: a
+    // thread's next chunk in the same block is `stride` chunks on, so its
+    // deposit follows by one masked add (the holes filled with ones carry
+    // through), and only a new block needs the bit-by-bit deposit.
+    int bi = -1;
+    uint32_t j0 = 0, hi0 = 0, dstep = 0;
     for (uint32_t ch = first; ch < sb.total_chunks; ch += stride) {
-        int bi = 0;
-        while (W.cpre[bi + 1] <= ch) ++bi;
+        const bool fresh = bi < 0 || ch >= W.cpre[bi + 1];
+        if (fresh) {
+            bi = bi < 0 ? 0 : bi;
+            while (W.cpre[bi + 1] <= ch) ++bi;
+        }
         const uint32_t b = W.blk[bi];
         const bool full = W.full[bi] != 0;
         const uint32_t lo = lowbit(b), rest = b ^ lo;
         const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
-        const uint32_t j0 = (ch - W.cpre[bi]) << sb.shift;
+        if (fresh) {
+            j0 = (ch - W.cpre[bi]) << sb.shift;
+            hi0 = deposit(j0, rest);
+            // a step that leaves the block's range is never taken: the next
+            // chunk is then in a later block
+            dstep = deposit(stride << sb.shift, rest);
+        } else {
+            j0 += stride << sb.shift;
+            hi0 = ((hi0 | ~rest) + dstep) & rest;
+        }
         const uint32_t j1 = min(j0 + (1u << sb.shift), hb);
         if (kChunkTables && !full && sb.shift == 4 && popc32(rest) >= 5) {
             // 16 candidates share the members of rest above its lowest four
@@ -976,7 +994,7 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
                            r3 = r2 ^ m2, m3 = lowbit(r3), low4 = m0 | m1 | m2 | m3;
             const uint32_t a0 = L.adj[ctz32(m0)], a1 = L.adj[ctz32(m1)], a2 = L.adj[ctz32(m2)],
                            a3 = L.adj[ctz32(m3)];
-            const uint32_t hi = deposit(j0, rest);             // j0 is a multiple of 16
+            const uint32_t hi = hi0;  // j0 is a multiple of 16
             const uint32_t H = lo | hi, RH = (rest & ~low4) & ~hi;
             const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH), N4 = a0 | a1 | a2 | a3;
             // the whole chunk is dead when a shared member on either side
@@ -1017,7 +1035,7 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
             }
             continue;
         }
-        uint32_t sub = deposit(j0, rest);
+        uint32_t sub = hi0;
         for (uint32_t j = j0; j < j1; ++j) {
             const uint32_t lb = lo | sub, rb = b ^ lb;
             sub = (sub - rest) & rest;

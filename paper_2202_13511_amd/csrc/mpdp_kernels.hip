@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
 // workgroup finds the blocks, all 16 waves share the candidate chunks, and
 // the plan keys are reduced through LDS.
 template <int CM>
-__global__ __launch_bounds__(kHeavyBlock) void k_eval_heavy(const DevGraph *g, uint32_t k, const uint32_t *heavy,
+__global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_eval_heavy(const DevGraph *g, uint32_t k, const uint32_t *heavy,
                                                             Counters *cnt, MemoPtrs M, HeavyPart *partrec) {
     constexpr int kHW = kHeavyBlock / 64;
     __shared__ __align__(16) LdsGraph L;
