@@ -611,6 +611,9 @@ void part_features(const Graph &G, Pool &P, const std::vector<Unit> &units,
         inc[pairs[e].second].push_back(w[e]);
     }
     X.assign(ne * MPDP_SCORER_IN, 0);
+    // candidates with a smaller weight than each: its place among them sorted
+    std::vector<double> wsorted(w);
+    std::sort(wsorted.begin(), wsorted.end());
     for (size_t e = 0; e < ne; ++e) {
         const uint32_t a = pairs[e].first, b = pairs[e].second;
         double f[MPDP_SCORER_IN] = {0.0};
@@ -623,7 +626,7 @@ void part_features(const Graph &G, Pool &P, const std::vector<Unit> &units,
         double ca = 0.0, cb = 0.0, cg = 0.0;
         for (double x : inc[a]) ca += x < w[e] ? 1.0 : 0.0;
         for (double x : inc[b]) cb += x < w[e] ? 1.0 : 0.0;
-        for (double x : w) cg += x < w[e] ? 1.0 : 0.0;
+        cg = (double)(std::lower_bound(wsorted.begin(), wsorted.end(), w[e]) - wsorted.begin());
         const double ra = ca / da, rb = cb / db;
         const double ma = lw - std::log10(*std::min_element(inc[a].begin(), inc[a].end()));
         const double mb = lw - std::log10(*std::min_element(inc[b].begin(), inc[b].end()));
