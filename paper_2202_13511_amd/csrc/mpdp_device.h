@@ -944,118 +944,174 @@ __device__ __forceinline__ void split_ranks(const LdsGraph &L, uint32_t S, uint3
     rr = b;
 }
 
-// Alg. 3 candidates of the chunks ch = first, first + stride, ... of S: for
-// each block-local lb holding the block's lowest relation (lb != block, so
-// each unordered pair is met once and both orientations are costed) the CCP
-// check is that G[lb] and G[rb] are connected (they are adjacent because the
-// block is); then S_left = grow(lb, S - rb) and S_right = S - S_left.
+// The pair of S from one Alg. 3 candidate whose two sides are connected:
+// S_left = grow(lb, S - rb) (lb when the block has no cut vertex of S), and
+// S_right = S - S_left, costed in both orientations.
+template <int CM>
+__device__ __forceinline__ void eval_lb(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t A, int k,
+                                        uint32_t lb, uint32_t rb, double cardS, Key &best,
+                                        unsigned long long &ccp) {
+    ++ccp;
+    const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
+    uint32_t rl, rr;
+    split_ranks(L, S, Sl, rl, rr);
+    const int kl = popc32(Sl);
+    eval_pair<CM>(M, Sl, S ^ Sl, L.loff[kl] + rl, L.loff[k - kl] + rr, cardS, best);
+}
+
+// A candidate (lb, rb) of a block: the CCP check (G[lb] and G[rb]
+// connected; they are adjacent because the block is), then its pair.
+template <int CM>
+__device__ __forceinline__ void check_lb(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t A, int k,
+                                         uint32_t lb, uint32_t rb, double cardS, Key &best,
+                                         unsigned long long &ccp) {
+    if (grow(L.nb, lowbit(lb), lb) != lb) return;
+    if (grow(L.nb, lowbit(rb), rb) != rb) return;
+    eval_lb<CM>(L, M, S, A, k, lb, rb, cardS, best, ccp);
+}
+
+// Survivor buffer of one wave (the candidates that pass the neighbourhood
+// tests, checked and costed 64 at a time).
+constexpr uint32_t kSurvCap = 128;
+
+// Alg. 3 candidates of S over the chunks ch = first, first + stride, ... of
+// its blocks: for each block-local lb holding the block's lowest relation
+// (lb != block, so each unordered pair is met once and both orientations
+// are costed) the CCP check, then S_left and S_right (eval_lb).  A thread's
+// next chunk in the same block is `stride` chunks on, so its first
+// candidate's deposit over the block's members follows by one masked add
+// (the holes filled with ones carry through); only a new block needs the
+// bit-by-bit deposit.
+//
+// With chunk tables (the per-level kernels; `first - lane` and `stride`
+// multiples of 64, so every wave walks its chunks together, and `sv` the
+// wave's survivor buffer): the candidates of a sparse block's chunk that
+// pass the neighbourhood tests go to the buffer, and whenever 64 are there
+// the wave checks and costs them with every lane busy, instead of each
+// lane walking its own few while the others wait.
 template <int CM, bool kChunkTables = true>
 __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M, const WaveScratch &W, uint32_t S,
                                             const SetBlocks &sb, uint32_t first, uint32_t stride, double cardS,
-                                            Key &best, unsigned long long &ccp) {
+                                            Key &best, unsigned long long &ccp, uint2 *sv = nullptr) {
     const int k = popc32(S);
     const uint32_t A = sb.A;
-    // The chunk's first candidate, deposited over the block's members: a
-    // thread's next chunk in the same block is `stride` chunks on, so its
-    // deposit follows by one masked add (the holes filled with ones carry
-    // through), and only a new block needs the bit-by-bit deposit.
+    const uint32_t lane = first & 63u;
+    const unsigned long long below_me = (1ull << lane) - 1ull;
     int bi = -1;
-    uint32_t j0 = 0, hi0 = 0, dstep = 0;
-    for (uint32_t ch = first; ch < sb.total_chunks; ch += stride) {
-        const bool fresh = bi < 0 || ch >= W.cpre[bi + 1];
-        if (fresh) {
-            bi = bi < 0 ? 0 : bi;
-            while (W.cpre[bi + 1] <= ch) ++bi;
-        }
-        const uint32_t b = W.blk[bi];
-        const bool full = W.full[bi] != 0;
-        const uint32_t lo = lowbit(b), rest = b ^ lo;
-        const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
-        if (fresh) {
-            j0 = (ch - W.cpre[bi]) << sb.shift;
-            hi0 = deposit(j0, rest);
-            // a step that leaves the block's range is never taken: the next
-            // chunk is then in a later block
-            dstep = deposit(stride << sb.shift, rest);
-        } else {
-            j0 += stride << sb.shift;
-            hi0 = ((hi0 | ~rest) + dstep) & rest;
-        }
-        const uint32_t j1 = min(j0 + (1u << sb.shift), hb);
-        if (kChunkTables && !full && sb.shift == 4 && popc32(rest) >= 5) {
-            // 16 candidates share the members of rest above its lowest four
-            // (`hi` in lb, the others of that part in rb) and differ in
-            // which of those four (low4) they take.  The neighbourhoods of
-            // the shared parts are looked up once per chunk and those of
-            // the 16 low combinations built from four adjacency rows, so
-            // the isolated-member test is a few register operations per
-            // candidate; survivors take the breadth-first checks.
-            const uint32_t m0 = lowbit(rest), r1 = rest ^ m0, m1 = lowbit(r1), r2 = r1 ^ m1, m2 = lowbit(r2),
-                           r3 = r2 ^ m2, m3 = lowbit(r3), low4 = m0 | m1 | m2 | m3;
-            const uint32_t a0 = L.adj[ctz32(m0)], a1 = L.adj[ctz32(m1)], a2 = L.adj[ctz32(m2)],
-                           a3 = L.adj[ctz32(m3)];
-            const uint32_t hi = hi0;  // j0 is a multiple of 16
-            const uint32_t H = lo | hi, RH = (rest & ~low4) & ~hi;
-            const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH), N4 = a0 | a1 | a2 | a3;
-            // the whole chunk is dead when a shared member on either side
-            // has no neighbour among its side's shared members and low4
-            // (that side then has two or more members in every candidate)
-            if (((H & (H - 1)) && (H & ~(NH | N4))) || ((RH & (RH - 1)) && (RH & ~(NRH | N4)))) continue;
-            // pass 1 (unrolled, registers only): which candidates survive;
-            // candidate t takes the members of low4 named by the bits of t
-            // (a compile-time choice, so each side's set and neighbourhood
-            // is at most three ORs of the four members and rows)
-            uint32_t live = 0;
+    uint32_t j0 = 0, hi0 = 0, dstep = 0, fill = 0;
+    const uint32_t base0 = kChunkTables ? first - lane : first, lane_off = kChunkTables ? lane : 0u;
+    for (uint32_t base = base0; base < sb.total_chunks; base += stride) {
+        const uint32_t ch = base + lane_off;
+        uint32_t pend = 0, H = 0, RH = 0, low4 = 0;
+        if (ch < sb.total_chunks) {
+            const bool fresh = bi < 0 || ch >= W.cpre[bi + 1];
+            if (fresh) {
+                bi = bi < 0 ? 0 : bi;
+                while (W.cpre[bi + 1] <= ch) ++bi;
+            }
+            const uint32_t b = W.blk[bi];
+            const bool full = W.full[bi] != 0;
+            const uint32_t lo = lowbit(b), rest = b ^ lo;
+            const uint32_t hb = (1u << (popc32(b) - 1)) - 1u;
+            if (fresh) {
+                j0 = (ch - W.cpre[bi]) << sb.shift;
+                hi0 = deposit(j0, rest);
+                // a step that leaves the block's range is never taken: the
+                // next chunk is then in a later block
+                dstep = deposit(stride << sb.shift, rest);
+            } else {
+                j0 += stride << sb.shift;
+                hi0 = ((hi0 | ~rest) + dstep) & rest;
+            }
+            const uint32_t j1 = min(j0 + (1u << sb.shift), hb);
+            if (kChunkTables && !full && sb.shift == 4 && popc32(rest) >= 5) {
+                // 16 candidates share the members of rest above its lowest four
+                // (`hi` in lb, the others of that part in rb) and differ in
+                // which of those four (low4) they take.  The neighbourhoods of
+                // the shared parts are looked up once per chunk and those of
+                // the 16 low combinations built from four adjacency rows, so
+                // the isolated-member test is a few register operations per
+                // candidate; the survivors go to the wave's buffer.
+                const uint32_t m0 = lowbit(rest), r1 = rest ^ m0, m1 = lowbit(r1), r2 = r1 ^ m1, m2 = lowbit(r2),
+                               m3 = lowbit(r2 ^ m2);
+                low4 = m0 | m1 | m2 | m3;
+                const uint32_t a0 = L.adj[ctz32(m0)], a1 = L.adj[ctz32(m1)], a2 = L.adj[ctz32(m2)],
+                               a3 = L.adj[ctz32(m3)];
+                const uint32_t hi = hi0;  // j0 is a multiple of 16
+                H = lo | hi;
+                RH = (rest & ~low4) & ~hi;
+                const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH), N4 = a0 | a1 | a2 | a3;
+                // the whole chunk is dead when a shared member on either side
+                // has no neighbour among its side's shared members and low4
+                // (that side then has two or more members in every candidate)
+                if (!(((H & (H - 1)) && (H & ~(NH | N4))) || ((RH & (RH - 1)) && (RH & ~(NRH | N4))))) {
+                    // pass 1 (unrolled, registers only): which candidates survive;
+                    // candidate t takes the members of low4 named by the bits of t
+                    // (a compile-time choice, so each side's set and neighbourhood
+                    // is at most three ORs of the four members and rows)
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const uint32_t ls = ((t & 1) ? m0 : 0u) | ((t & 2) ? m1 : 0u) | ((t & 4) ? m2 : 0u) |
-                                    ((t & 8) ? m3 : 0u);
-                const uint32_t nl = ((t & 1) ? a0 : 0u) | ((t & 2) ? a1 : 0u) | ((t & 4) ? a2 : 0u) |
-                                    ((t & 8) ? a3 : 0u);
-                const uint32_t nr = ((t & 1) ? 0u : a0) | ((t & 2) ? 0u : a1) | ((t & 4) ? 0u : a2) |
-                                    ((t & 8) ? 0u : a3);
-                const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
-                const bool dead = ((lb & (lb - 1)) && (lb & ~(NH | nl))) || ((rb & (rb - 1)) && (rb & ~(NRH | nr)));
-                live |= (!dead && j0 + (uint32_t)t < j1) ? (1u << t) : 0u;
+                    for (int t = 0; t < 16; ++t) {
+                        const uint32_t ls = ((t & 1) ? m0 : 0u) | ((t & 2) ? m1 : 0u) | ((t & 4) ? m2 : 0u) |
+                                            ((t & 8) ? m3 : 0u);
+                        const uint32_t nl = ((t & 1) ? a0 : 0u) | ((t & 2) ? a1 : 0u) | ((t & 4) ? a2 : 0u) |
+                                            ((t & 8) ? a3 : 0u);
+                        const uint32_t nr = ((t & 1) ? 0u : a0) | ((t & 2) ? 0u : a1) | ((t & 4) ? 0u : a2) |
+                                            ((t & 8) ? 0u : a3);
+                        const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
+                        const bool dead = ((lb & (lb - 1)) && (lb & ~(NH | nl))) || ((rb & (rb - 1)) && (rb & ~(NRH | nr)));
+                        pend |= (!dead && j0 + (uint32_t)t < j1) ? (1u << t) : 0u;
+                    }
+                }
+            } else {
+                uint32_t sub = hi0;
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const uint32_t lb = lo | sub, rb = b ^ lb;
+                    sub = (sub - rest) & rest;
+                    if (!full) {
+                        // a connected side of two or more relations has no
+                        // member without a neighbour on its side: four table
+                        // lookups reject most disconnected candidates of a
+                        // sparse block before the breadth-first check
+                        if ((lb & (lb - 1)) && (lb & ~nbrs(L.nb, lb))) continue;
+                        if ((rb & (rb - 1)) && (rb & ~nbrs(L.nb, rb))) continue;
+                        if (grow(L.nb, lo, lb) != lb) continue;
+                        if (grow(L.nb, lowbit(rb), rb) != rb) continue;
+                    }
+                    eval_lb<CM>(L, M, S, A, k, lb, rb, cardS, best, ccp);
+                }
             }
-            // pass 2: the survivors' breadth-first checks and costs
-            for (uint32_t Lm = live; Lm; Lm &= Lm - 1) {
+        }
+        if (!kChunkTables) continue;
+        // this round's survivors into the wave's buffer (as many as fit),
+        // then 64 at a time out of it, until every lane has placed its own
+        while (__ballot(pend != 0) != 0ull) {
+            const uint32_t c = (uint32_t)popc32(pend);  // at most 16
+            uint32_t before = 0;
+#pragma unroll
+            for (int bt = 0; bt < 5; ++bt)
+                before += (uint32_t)__popcll(__ballot((c >> bt) & 1u) & below_me) << bt;
+            const uint32_t total = (uint32_t)__shfl((int)(before + c), 63);
+            uint32_t slot = fill + before;
+            for (uint32_t Lm = pend; Lm && slot < kSurvCap; Lm &= Lm - 1, ++slot) {
                 const uint32_t t = (uint32_t)ctz32(Lm);
-                const uint32_t ls = ((t & 1u) ? m0 : 0u) | ((t & 2u) ? m1 : 0u) | ((t & 4u) ? m2 : 0u) |
-                                    ((t & 8u) ? m3 : 0u);
-                const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
-                if (grow(L.nb, lo, lb) != lb) continue;
-                if (grow(L.nb, lowbit(rb), rb) != rb) continue;
-                ++ccp;
-                const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
-                uint32_t rl, rr;
-                split_ranks(L, S, Sl, rl, rr);
-                const int kl = popc32(Sl);
-                eval_pair<CM>(M, Sl, S ^ Sl, L.loff[kl] + rl, L.loff[k - kl] + rr, cardS, best);
+                const uint32_t ls = deposit(t, low4);
+                sv[slot] = make_uint2(H | ls, RH | (low4 ^ ls));
+                pend &= ~(1u << t);
             }
-            continue;
-        }
-        uint32_t sub = hi0;
-        for (uint32_t j = j0; j < j1; ++j) {
-            const uint32_t lb = lo | sub, rb = b ^ lb;
-            sub = (sub - rest) & rest;
-            if (!full) {
-                // a connected side of two or more relations has no member
-                // without a neighbour on its side: four table lookups
-                // reject most disconnected candidates of a sparse block
-                // before the breadth-first check
-                if ((lb & (lb - 1)) && (lb & ~nbrs(L.nb, lb))) continue;
-                if ((rb & (rb - 1)) && (rb & ~nbrs(L.nb, rb))) continue;
-                if (grow(L.nb, lo, lb) != lb) continue;
-                if (grow(L.nb, lowbit(rb), rb) != rb) continue;
+            fill = min(kSurvCap, fill + total);
+            wave_sync_lds();
+            while (fill >= 64u) {
+                const uint2 e = sv[fill - 64u + lane];
+                fill -= 64u;
+                wave_sync_lds();
+                check_lb<CM>(L, M, S, A, k, e.x, e.y, cardS, best, ccp);
             }
-            ++ccp;
-            const uint32_t Sl = (lb & A) ? grow(L.nb, lb, S & ~rb) : lb;
-            uint32_t rl, rr;
-            split_ranks(L, S, Sl, rl, rr);
-            const int kl = popc32(Sl);
-            eval_pair<CM>(M, Sl, S ^ Sl, L.loff[kl] + rl, L.loff[k - kl] + rr, cardS, best);
         }
+    }
+    if (kChunkTables && fill != 0u) {
+        const uint2 e = lane < fill ? sv[lane] : make_uint2(0u, 0u);
+        wave_sync_lds();
+        if (lane < fill) check_lb<CM>(L, M, S, A, k, e.x, e.y, cardS, best, ccp);
     }
 }
 
@@ -1334,7 +1390,7 @@ template <int CM, bool kChunkTables = true>
 __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *list, uint32_t cap, uint32_t ntree,
                            uint32_t ngen, uint32_t w0, uint32_t wstride, WaveScratch &W, uint32_t *heavy,
                            uint32_t *nheavy, uint32_t lane, unsigned long long &ccp, unsigned long long &evaluated,
-                           bool dpsub = false, uint32_t heavy_chunks = kHeavyChunks) {
+                           bool dpsub = false, uint32_t heavy_chunks = kHeavyChunks, uint2 *sv = nullptr) {
     const uint32_t groups = (ntree + 63u) >> 6;
     for (uint32_t i = w0; i < groups + ngen; i += wstride) {
         if (i < groups) {
@@ -1357,7 +1413,7 @@ __device__ void light_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t 
         wave_sync_lds();
         const double cardS = card_of_wave(L, S, lane);
         Key best = worst_key();
-        eval_chunks<CM, kChunkTables>(L, M, W, S, sb, lane, 64u, cardS, best, ccp);
+        eval_chunks<CM, kChunkTables>(L, M, W, S, sb, lane, 64u, cardS, best, ccp, sv);
         best = wave_min(best);
         const uint64_t at = memo_index_wave(L, S, lane);
         if (lane == 0) store_best(M, at, best, cardS);

@@ -150,12 +150,14 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
                                                          uint32_t *heavy, Counters *cnt, MemoPtrs M) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ WaveScratch WS[kWaves];
+    __shared__ uint2 SV[kWaves][kSurvCap];
     stage_graph(g, L);
     const uint32_t lane = threadIdx.x & 63u, n = g->n;
     unsigned long long my_ccp = 0, my_eval = 0;
     light_sets<CM>(L, M, list, L.binom[n * 33 + n / 2], cnt->level_count[k], cnt->general_count[k],
                    blockIdx.x * kWaves + (threadIdx.x >> 6), gridDim.x * kWaves, WS[threadIdx.x >> 6], heavy,
-                   &cnt->heavy_count[k], lane, my_ccp, my_eval, (g->ablate & kAblateDpsub) != 0);
+                   &cnt->heavy_count[k], lane, my_ccp, my_eval, (g->ablate & kAblateDpsub) != 0, kHeavyChunks,
+                   SV[threadIdx.x >> 6]);
 
     // one atomic per wave for the counters
     for (int off = 32; off >= 1; off >>= 1) {
@@ -183,6 +185,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8, 
     __shared__ WaveScratch W;
     __shared__ SetBlocks sbs;
     __shared__ Key keys[kHW];
+    __shared__ uint2 SV[kHW][kSurvCap];
     const uint32_t count = cnt->heavy_count[k];
     const uint32_t parts = heavy_parts(count, gridDim.x);
     if (blockIdx.x >= count * parts) return;  // the whole workgroup, before any barrier
@@ -201,7 +204,8 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8, 
         const SetBlocks sb = sbs;
         const double cardS = card_of_wave(L, S, threadIdx.x & 63u);
         Key best = worst_key();
-        eval_chunks<CM>(L, M, W, S, sb, part * kHeavyBlock + threadIdx.x, parts * kHeavyBlock, cardS, best, my_ccp);
+        eval_chunks<CM>(L, M, W, S, sb, part * kHeavyBlock + threadIdx.x, parts * kHeavyBlock, cardS, best, my_ccp,
+                        SV[wave]);
         best = wave_min(best);
         if (lane == 0) keys[wave] = best;
         __syncthreads();
