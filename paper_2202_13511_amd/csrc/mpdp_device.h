@@ -959,20 +959,36 @@ __device__ __forceinline__ void eval_lb(const LdsGraph &L, const MemoPtrs &M, ui
     eval_pair<CM>(M, Sl, S ^ Sl, L.loff[kl] + rl, L.loff[k - kl] + rr, cardS, best);
 }
 
-// A candidate (lb, rb) of a block: the CCP check (G[lb] and G[rb]
-// connected; they are adjacent because the block is), then its pair.
-template <int CM>
-__device__ __forceinline__ void check_lb(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t A, int k,
-                                         uint32_t lb, uint32_t rb, double cardS, Key &best,
-                                         unsigned long long &ccp) {
-    if (grow(L.nb, lowbit(lb), lb) != lb) return;
-    if (grow(L.nb, lowbit(rb), rb) != rb) return;
-    eval_lb<CM>(L, M, S, A, k, lb, rb, cardS, best, ccp);
+// The CCP check of a candidate (lb, rb) of a block: G[lb] and G[rb]
+// connected (they are adjacent because the block is).
+__device__ __forceinline__ bool ccp_lb(const LdsGraph &L, uint32_t lb, uint32_t rb) {
+    return grow(L.nb, lowbit(lb), lb) == lb && grow(L.nb, lowbit(rb), rb) == rb;
 }
 
-// Survivor buffer of one wave (the candidates that pass the neighbourhood
-// tests, checked and costed 64 at a time).
+// Buffers of one wave: the candidates that pass the neighbourhood tests
+// (entries 0 .. kSurvCap - 1), checked 64 at a time, and the ones that pass
+// the CCP check (the next kSurvCap entries), costed 64 at a time.
 constexpr uint32_t kSurvCap = 128;
+
+// One candidate per lane (`ok`: it passed the CCP check) appended to the
+// wave's buffer of valid pairs `vb` (vfill < 64 entries there, uniform);
+// 64 of them are costed together once there are.
+template <int CM>
+__device__ __forceinline__ void push_valid(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t A, int k,
+                                           uint2 e, bool ok, uint2 *vb, uint32_t &vfill, uint32_t lane,
+                                           unsigned long long below_me, double cardS, Key &best,
+                                           unsigned long long &ccp) {
+    const unsigned long long m = __ballot(ok);
+    if (ok) vb[vfill + (uint32_t)__popcll(m & below_me)] = e;
+    vfill += (uint32_t)__popcll(m);
+    wave_sync_lds();
+    if (vfill >= 64u) {
+        const uint2 v = vb[vfill - 64u + lane];
+        vfill -= 64u;
+        wave_sync_lds();
+        eval_lb<CM>(L, M, S, A, k, v.x, v.y, cardS, best, ccp);
+    }
+}
 
 // Alg. 3 candidates of S over the chunks ch = first, first + stride, ... of
 // its blocks: for each block-local lb holding the block's lowest relation
@@ -998,7 +1014,7 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
     const uint32_t lane = first & 63u;
     const unsigned long long below_me = (1ull << lane) - 1ull;
     int bi = -1;
-    uint32_t j0 = 0, hi0 = 0, dstep = 0, fill = 0;
+    uint32_t j0 = 0, hi0 = 0, dstep = 0, fill = 0, vfill = 0;
     const uint32_t base0 = kChunkTables ? first - lane : first, lane_off = kChunkTables ? lane : 0u;
     for (uint32_t base = base0; base < sb.total_chunks; base += stride) {
         const uint32_t ch = base + lane_off;
@@ -1104,14 +1120,23 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
                 const uint2 e = sv[fill - 64u + lane];
                 fill -= 64u;
                 wave_sync_lds();
-                check_lb<CM>(L, M, S, A, k, e.x, e.y, cardS, best, ccp);
+                push_valid<CM>(L, M, S, A, k, e, ccp_lb(L, e.x, e.y), sv + kSurvCap, vfill, lane, below_me, cardS,
+                               best, ccp);
             }
         }
     }
-    if (kChunkTables && fill != 0u) {
-        const uint2 e = lane < fill ? sv[lane] : make_uint2(0u, 0u);
-        wave_sync_lds();
-        if (lane < fill) check_lb<CM>(L, M, S, A, k, e.x, e.y, cardS, best, ccp);
+    if (kChunkTables) {
+        if (fill != 0u) {
+            const uint2 e = lane < fill ? sv[lane] : make_uint2(0u, 0u);
+            wave_sync_lds();
+            push_valid<CM>(L, M, S, A, k, e, lane < fill && ccp_lb(L, e.x, e.y), sv + kSurvCap, vfill, lane,
+                           below_me, cardS, best, ccp);
+        }
+        if (vfill != 0u) {
+            const uint2 e = lane < vfill ? sv[kSurvCap + lane] : make_uint2(0u, 0u);
+            wave_sync_lds();
+            if (lane < vfill) eval_lb<CM>(L, M, S, A, k, e.x, e.y, cardS, best, ccp);
+        }
     }
 }
 
