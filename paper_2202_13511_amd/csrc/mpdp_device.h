@@ -965,9 +965,9 @@ __device__ __forceinline__ bool ccp_lb(const LdsGraph &L, uint32_t lb, uint32_t 
     return grow(L.nb, lowbit(lb), lb) == lb && grow(L.nb, lowbit(rb), rb) == rb;
 }
 
-// Buffers of one wave: the candidates that pass the neighbourhood tests
-// (entries 0 .. kSurvCap - 1), checked 64 at a time, and the ones that pass
-// the CCP check (the next kSurvCap entries), costed 64 at a time.
+// Buffers of one wave, kSurvCap entries each: the candidates that pass the
+// neighbourhood tests (checked 64 at a time), the ones that pass the CCP
+// check (costed 64 at a time), and the live chunks (tested 64 at a time).
 constexpr uint32_t kSurvCap = 128;
 
 // One candidate per lane (`ok`: it passed the CCP check) appended to the
@@ -987,6 +987,71 @@ __device__ __forceinline__ void push_valid(const LdsGraph &L, const MemoPtrs &M,
         vfill -= 64u;
         wave_sync_lds();
         eval_lb<CM>(L, M, S, A, k, v.x, v.y, cardS, best, ccp);
+    }
+}
+
+// Pass 1 of a live chunk from the chunk buffer (entry: the deposit of its
+// shared members, and its block index << 8 | its candidate count): the
+// neighbourhoods of the shared parts are looked up once and those of the
+// 16 low combinations built from four adjacency rows, so the isolated-member
+// test is a few register operations per candidate (candidate t takes the
+// members of low4 named by the bits of t, a compile-time choice).  Returns
+// the surviving candidates as a 16-bit mask with the chunk's H, RH, low4.
+__device__ __forceinline__ void chunk_pass1(const LdsGraph &L, const WaveScratch &W, uint2 e, uint32_t &pend,
+                                            uint32_t &H, uint32_t &RH, uint32_t &low4) {
+    const uint32_t b = W.blk[e.y >> 8], lim = e.y & 255u;
+    const uint32_t lo = lowbit(b), rest = b ^ lo;
+    const uint32_t m0 = lowbit(rest), r1 = rest ^ m0, m1 = lowbit(r1), r2 = r1 ^ m1, m2 = lowbit(r2),
+                   m3 = lowbit(r2 ^ m2);
+    low4 = m0 | m1 | m2 | m3;
+    const uint32_t a0 = L.adj[ctz32(m0)], a1 = L.adj[ctz32(m1)], a2 = L.adj[ctz32(m2)], a3 = L.adj[ctz32(m3)];
+    H = lo | e.x;
+    RH = (rest & ~low4) & ~e.x;
+    const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH);
+    pend = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const uint32_t ls = ((t & 1) ? m0 : 0u) | ((t & 2) ? m1 : 0u) | ((t & 4) ? m2 : 0u) | ((t & 8) ? m3 : 0u);
+        const uint32_t nl = ((t & 1) ? a0 : 0u) | ((t & 2) ? a1 : 0u) | ((t & 4) ? a2 : 0u) | ((t & 8) ? a3 : 0u);
+        const uint32_t nr = ((t & 1) ? 0u : a0) | ((t & 2) ? 0u : a1) | ((t & 4) ? 0u : a2) | ((t & 8) ? 0u : a3);
+        const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
+        const bool dead = ((lb & (lb - 1)) && (lb & ~(NH | nl))) || ((rb & (rb - 1)) && (rb & ~(NRH | nr)));
+        pend |= (!dead && (uint32_t)t < lim) ? (1u << t) : 0u;
+    }
+}
+
+// Every lane's surviving candidates (pend) into the wave's survivor buffer
+// (as many as fit), then 64 at a time out of it through the CCP check, until
+// every lane has placed its own.
+template <int CM>
+__device__ __forceinline__ void place_survivors(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t A, int k,
+                                                uint32_t pend, uint32_t H, uint32_t RH, uint32_t low4, uint2 *sv,
+                                                uint32_t &fill, uint32_t &vfill, uint32_t lane,
+                                                unsigned long long below_me, double cardS, Key &best,
+                                                unsigned long long &ccp) {
+    while (__ballot(pend != 0) != 0ull) {
+        const uint32_t c = (uint32_t)popc32(pend);  // at most 16
+        uint32_t before = 0;
+#pragma unroll
+        for (int bt = 0; bt < 5; ++bt)
+            before += (uint32_t)__popcll(__ballot((c >> bt) & 1u) & below_me) << bt;
+        const uint32_t total = (uint32_t)__shfl((int)(before + c), 63);
+        uint32_t slot = fill + before;
+        for (uint32_t Lm = pend; Lm && slot < kSurvCap; Lm &= Lm - 1, ++slot) {
+            const uint32_t t = (uint32_t)ctz32(Lm);
+            const uint32_t ls = deposit(t, low4);
+            sv[slot] = make_uint2(H | ls, RH | (low4 ^ ls));
+            pend &= ~(1u << t);
+        }
+        fill = min(kSurvCap, fill + total);
+        wave_sync_lds();
+        while (fill >= 64u) {
+            const uint2 e = sv[fill - 64u + lane];
+            fill -= 64u;
+            wave_sync_lds();
+            push_valid<CM>(L, M, S, A, k, e, ccp_lb(L, e.x, e.y), sv + kSurvCap, vfill, lane, below_me, cardS, best,
+                           ccp);
+        }
     }
 }
 
@@ -1014,11 +1079,13 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
     const uint32_t lane = first & 63u;
     const unsigned long long below_me = (1ull << lane) - 1ull;
     int bi = -1;
-    uint32_t j0 = 0, hi0 = 0, dstep = 0, fill = 0, vfill = 0;
+    uint32_t j0 = 0, hi0 = 0, dstep = 0, fill = 0, vfill = 0, cfill = 0;
+    uint2 *cb = sv + 2u * kSurvCap;
     const uint32_t base0 = kChunkTables ? first - lane : first, lane_off = kChunkTables ? lane : 0u;
     for (uint32_t base = base0; base < sb.total_chunks; base += stride) {
         const uint32_t ch = base + lane_off;
-        uint32_t pend = 0, H = 0, RH = 0, low4 = 0;
+        bool alive = false;
+        uint2 centry = make_uint2(0u, 0u);
         if (ch < sb.total_chunks) {
             const bool fresh = bi < 0 || ch >= W.cpre[bi + 1];
             if (fresh) {
@@ -1041,42 +1108,21 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
             }
             const uint32_t j1 = min(j0 + (1u << sb.shift), hb);
             if (kChunkTables && !full && sb.shift == 4 && popc32(rest) >= 5) {
-                // 16 candidates share the members of rest above its lowest four
-                // (`hi` in lb, the others of that part in rb) and differ in
-                // which of those four (low4) they take.  The neighbourhoods of
-                // the shared parts are looked up once per chunk and those of
-                // the 16 low combinations built from four adjacency rows, so
-                // the isolated-member test is a few register operations per
-                // candidate; the survivors go to the wave's buffer.
+                // 16 candidates share the members of rest above its lowest
+                // four (`hi` in lb, the others of that part in rb) and differ
+                // in which of those four (low4) they take.  The chunk is dead
+                // when a shared member on either side has no neighbour among
+                // its side's shared members and low4 (that side then has two
+                // or more members in every candidate); a live chunk goes to
+                // the wave's chunk buffer (chunk_pass1).
                 const uint32_t m0 = lowbit(rest), r1 = rest ^ m0, m1 = lowbit(r1), r2 = r1 ^ m1, m2 = lowbit(r2),
-                               m3 = lowbit(r2 ^ m2);
-                low4 = m0 | m1 | m2 | m3;
-                const uint32_t a0 = L.adj[ctz32(m0)], a1 = L.adj[ctz32(m1)], a2 = L.adj[ctz32(m2)],
-                               a3 = L.adj[ctz32(m3)];
-                const uint32_t hi = hi0;  // j0 is a multiple of 16
-                H = lo | hi;
-                RH = (rest & ~low4) & ~hi;
-                const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH), N4 = a0 | a1 | a2 | a3;
-                // the whole chunk is dead when a shared member on either side
-                // has no neighbour among its side's shared members and low4
-                // (that side then has two or more members in every candidate)
+                               m3 = lowbit(r2 ^ m2), low4 = m0 | m1 | m2 | m3;
+                const uint32_t N4 = L.adj[ctz32(m0)] | L.adj[ctz32(m1)] | L.adj[ctz32(m2)] | L.adj[ctz32(m3)];
+                const uint32_t H = lo | hi0, RH = (rest & ~low4) & ~hi0;  // j0 is a multiple of 16
+                const uint32_t NH = nbrs(L.nb, H), NRH = nbrs(L.nb, RH);
                 if (!(((H & (H - 1)) && (H & ~(NH | N4))) || ((RH & (RH - 1)) && (RH & ~(NRH | N4))))) {
-                    // pass 1 (unrolled, registers only): which candidates survive;
-                    // candidate t takes the members of low4 named by the bits of t
-                    // (a compile-time choice, so each side's set and neighbourhood
-                    // is at most three ORs of the four members and rows)
-#pragma unroll
-                    for (int t = 0; t < 16; ++t) {
-                        const uint32_t ls = ((t & 1) ? m0 : 0u) | ((t & 2) ? m1 : 0u) | ((t & 4) ? m2 : 0u) |
-                                            ((t & 8) ? m3 : 0u);
-                        const uint32_t nl = ((t & 1) ? a0 : 0u) | ((t & 2) ? a1 : 0u) | ((t & 4) ? a2 : 0u) |
-                                            ((t & 8) ? a3 : 0u);
-                        const uint32_t nr = ((t & 1) ? 0u : a0) | ((t & 2) ? 0u : a1) | ((t & 4) ? 0u : a2) |
-                                            ((t & 8) ? 0u : a3);
-                        const uint32_t lb = H | ls, rb = RH | (low4 ^ ls);
-                        const bool dead = ((lb & (lb - 1)) && (lb & ~(NH | nl))) || ((rb & (rb - 1)) && (rb & ~(NRH | nr)));
-                        pend |= (!dead && j0 + (uint32_t)t < j1) ? (1u << t) : 0u;
-                    }
+                    alive = true;
+                    centry = make_uint2(hi0, ((uint32_t)bi << 8) | (j1 - j0));
                 }
             } else {
                 uint32_t sub = hi0;
@@ -1098,34 +1144,30 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
             }
         }
         if (!kChunkTables) continue;
-        // this round's survivors into the wave's buffer (as many as fit),
-        // then 64 at a time out of it, until every lane has placed its own
-        while (__ballot(pend != 0) != 0ull) {
-            const uint32_t c = (uint32_t)popc32(pend);  // at most 16
-            uint32_t before = 0;
-#pragma unroll
-            for (int bt = 0; bt < 5; ++bt)
-                before += (uint32_t)__popcll(__ballot((c >> bt) & 1u) & below_me) << bt;
-            const uint32_t total = (uint32_t)__shfl((int)(before + c), 63);
-            uint32_t slot = fill + before;
-            for (uint32_t Lm = pend; Lm && slot < kSurvCap; Lm &= Lm - 1, ++slot) {
-                const uint32_t t = (uint32_t)ctz32(Lm);
-                const uint32_t ls = deposit(t, low4);
-                sv[slot] = make_uint2(H | ls, RH | (low4 ^ ls));
-                pend &= ~(1u << t);
-            }
-            fill = min(kSurvCap, fill + total);
+        // this round's live chunks into the wave's chunk buffer; once 64
+        // are there, each lane tests the 16 candidates of one of them and
+        // the survivors go on to the survivor buffer
+        const unsigned long long am = __ballot(alive);
+        if (alive) cb[cfill + (uint32_t)__popcll(am & below_me)] = centry;
+        cfill += (uint32_t)__popcll(am);
+        wave_sync_lds();
+        if (cfill >= 64u) {
+            const uint2 ce = cb[cfill - 64u + lane];
+            cfill -= 64u;
             wave_sync_lds();
-            while (fill >= 64u) {
-                const uint2 e = sv[fill - 64u + lane];
-                fill -= 64u;
-                wave_sync_lds();
-                push_valid<CM>(L, M, S, A, k, e, ccp_lb(L, e.x, e.y), sv + kSurvCap, vfill, lane, below_me, cardS,
-                               best, ccp);
-            }
+            uint32_t pend, H, RH, low4;
+            chunk_pass1(L, W, ce, pend, H, RH, low4);
+            place_survivors<CM>(L, M, S, A, k, pend, H, RH, low4, sv, fill, vfill, lane, below_me, cardS, best, ccp);
         }
     }
     if (kChunkTables) {
+        if (cfill != 0u) {
+            const uint2 ce = lane < cfill ? cb[lane] : make_uint2(0u, 1u);  // an empty chunk: no candidate
+            wave_sync_lds();
+            uint32_t pend = 0, H = 0, RH = 0, low4 = 0;
+            if (lane < cfill) chunk_pass1(L, W, ce, pend, H, RH, low4);
+            place_survivors<CM>(L, M, S, A, k, pend, H, RH, low4, sv, fill, vfill, lane, below_me, cardS, best, ccp);
+        }
         if (fill != 0u) {
             const uint2 e = lane < fill ? sv[lane] : make_uint2(0u, 0u);
             wave_sync_lds();

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
                                                          uint32_t *heavy, Counters *cnt, MemoPtrs M) {
     __shared__ __align__(16) LdsGraph L;
     __shared__ WaveScratch WS[kWaves];
-    __shared__ uint2 SV[kWaves][2 * kSurvCap];
+    __shared__ uint2 SV[kWaves][3 * kSurvCap];
     stage_graph(g, L);
     const uint32_t lane = threadIdx.x & 63u, n = g->n;
     unsigned long long my_ccp = 0, my_eval = 0;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8, 
     __shared__ WaveScratch W;
     __shared__ SetBlocks sbs;
     __shared__ Key keys[kHW];
-    __shared__ uint2 SV[kHW][2 * kSurvCap];
+    __shared__ uint2 SV[kHW][3 * kSurvCap];
     const uint32_t count = cnt->heavy_count[k];
     const uint32_t parts = heavy_parts(count, gridDim.x);
     if (blockIdx.x >= count * parts) return;  // the whole workgroup, before any barrier
