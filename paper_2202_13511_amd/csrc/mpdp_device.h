@@ -932,13 +932,28 @@ __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, 
 }
 
 // Colex ranks of Sl and of S - Sl in one pass over the members of S.
+// A member's place on its side is a popcount, so the table reads of four
+// members at a time are issued together (slots past the last member read
+// C(0, 1) and are masked).
 __device__ __forceinline__ void split_ranks(const LdsGraph &L, uint32_t S, uint32_t Sl, uint32_t &rl, uint32_t &rr) {
+    const uint32_t Sr = S & ~Sl;
     uint32_t a = 0, b = 0;
-    int il = 1, ir = 1;
-    for (uint32_t T = S; T; T &= T - 1) {
-        const int v = ctz32(T);
-        if ((Sl >> v) & 1u) a += L.binom[v * 33 + il++];
-        else b += L.binom[v * 33 + ir++];
+    for (uint32_t T = S; T;) {
+        uint32_t c[4], on[4], left[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t v = (uint32_t)ctz32(T | 0x80000000u), below = (1u << v) - 1u;
+            on[u] = T != 0u;
+            left[u] = (Sl >> v) & 1u;
+            const uint32_t place = (uint32_t)popc32((left[u] ? Sl : Sr) & below) + 1u;
+            c[u] = L.binom[on[u] ? v * 33u + place : 1u];
+            T &= T - 1u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a += (on[u] && left[u]) ? c[u] : 0u;
+            b += (on[u] && !left[u]) ? c[u] : 0u;
+        }
     }
     rl = a;
     rr = b;
