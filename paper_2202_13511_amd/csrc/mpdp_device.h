@@ -852,6 +852,22 @@ __device__ SetBlocks analyze_set(const LdsGraph &L, uint32_t S, WaveScratch &W, 
     const bool mine = lane < 32 && ((S >> lane) & 1u);
     const uint32_t adjS = mine ? (L.adj[lane] & S) : 0u;
 
+    // 0. a complete G[S] (every set of a clique) is one complete block with
+    // no cut vertex: what the search below finds, without its serial steps
+    if (__ballot(mine && (adjS | (1u << lane)) != S) == 0ull) {
+        const int k = popc32(S);
+        const uint32_t half = (1u << (k - 1)) - 1u;
+        const uint32_t c[5] = {half, (half + 1u) >> 1, (half + 3u) >> 2, (half + 7u) >> 3, (half + 15u) >> 4};
+        const uint32_t shift = c[0] <= budget ? 0u : c[1] <= budget ? 1u : c[2] <= budget ? 2u : c[3] <= budget ? 3u : 4u;
+        if (lane == 0) {
+            W.blk[0] = S;
+            W.full[0] = 1u;
+            W.cpre[0] = 0u;
+            W.cpre[1] = c[shift];
+        }
+        return SetBlocks{0u, c[shift], shift, c[4], c[4], (1ull << k) - 2ull};
+    }
+
     // 1. depth-first search: k - 1 steps down, k - 1 back up, one final test
     const uint32_t root = (uint32_t)ctz32(S);
     uint32_t par = 0, desc = mine ? (1u << lane) : 0u;
