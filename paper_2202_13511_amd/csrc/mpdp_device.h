@@ -40,6 +40,7 @@ constexpr uint64_t kTreeSplitMaxCand = 4096;
 constexpr uint32_t kHeavyChunks = MPDP_HEAVY_CHUNKS;   // above this many 16-candidate chunks a set is heavy
 constexpr int kHeavyBlock = 1024;        // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
+constexpr uint32_t kGeneralGrid = 1024;  // workgroups of a block-based level's light sets
 
 // Sets a lane evaluates at once in k_level_tree (independent chains,
 // interleaved): two under C_out, one under PG-like, whose gathers and
