@@ -1030,7 +1030,7 @@ __device__ __forceinline__ void push_valid(const LdsGraph &L, const MemoPtrs &M,
 // members of low4 named by the bits of t, a compile-time choice).  Returns
 // the surviving candidates as a 16-bit mask with the chunk's H, RH, low4.
 __device__ __forceinline__ void chunk_pass1(const LdsGraph &L, const WaveScratch &W, uint2 e, uint32_t &pend,
-                                            uint32_t &H, uint32_t &RH, uint32_t &low4) {
+                                            uint32_t &H, uint32_t &RH, uint32_t &low4, uint4 &edges) {
     const uint32_t b = W.blk[e.y >> 8], lim = e.y & 255u;
     const uint32_t lo = lowbit(b), rest = b ^ lo;
     const uint32_t m0 = lowbit(rest), r1 = rest ^ m0, m1 = lowbit(r1), r2 = r1 ^ m1, m2 = lowbit(r2),
@@ -1050,6 +1050,39 @@ __device__ __forceinline__ void chunk_pass1(const LdsGraph &L, const WaveScratch
         const bool dead = ((lb & (lb - 1)) && (lb & ~(NH | nl))) || ((rb & (rb - 1)) && (rb & ~(NRH | nr)));
         pend |= (!dead && (uint32_t)t < lim) ? (1u << t) : 0u;
     }
+    // for the survivors' edge test (place_survivors): twice the edges inside
+    // H and inside RH, each low member's edges to H and to RH (one byte
+    // each), and which pairs of low members are adjacent (bit i*4+j)
+    uint32_t eH2 = 0, eR2 = 0;
+    if (pend) {
+        for (uint32_t X = H; X;) {
+            uint32_t a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = X ? L.adj[ctz32(X)] : 0u;
+                X &= X - 1u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) eH2 += (uint32_t)popc32(a[u] & H);
+        }
+        for (uint32_t X = RH; X;) {
+            uint32_t a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = X ? L.adj[ctz32(X)] : 0u;
+                X &= X - 1u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) eR2 += (uint32_t)popc32(a[u] & RH);
+        }
+    }
+    const uint32_t cH = (uint32_t)popc32(a0 & H) | ((uint32_t)popc32(a1 & H) << 8) |
+                        ((uint32_t)popc32(a2 & H) << 16) | ((uint32_t)popc32(a3 & H) << 24);
+    const uint32_t cR = (uint32_t)popc32(a0 & RH) | ((uint32_t)popc32(a1 & RH) << 8) |
+                        ((uint32_t)popc32(a2 & RH) << 16) | ((uint32_t)popc32(a3 & RH) << 24);
+    const uint32_t adjl = ((a0 & m1) ? 0x0002u : 0u) | ((a0 & m2) ? 0x0004u : 0u) | ((a0 & m3) ? 0x0008u : 0u) |
+                          ((a1 & m2) ? 0x0040u : 0u) | ((a1 & m3) ? 0x0080u : 0u) | ((a2 & m3) ? 0x0800u : 0u);
+    edges = make_uint4(eH2 | (eR2 << 16), cH, cR, adjl);
 }
 
 // Every lane's surviving candidates (pend) into the wave's survivor buffer
@@ -1057,10 +1090,37 @@ __device__ __forceinline__ void chunk_pass1(const LdsGraph &L, const WaveScratch
 // every lane has placed its own.
 template <int CM>
 __device__ __forceinline__ void place_survivors(const LdsGraph &L, const MemoPtrs &M, uint32_t S, uint32_t A, int k,
-                                                uint32_t pend, uint32_t H, uint32_t RH, uint32_t low4, uint2 *sv,
-                                                uint32_t &fill, uint32_t &vfill, uint32_t lane,
+                                                uint32_t pend, uint32_t H, uint32_t RH, uint32_t low4, uint4 edges,
+                                                uint2 *sv, uint32_t &fill, uint32_t &vfill, uint32_t lane,
                                                 unsigned long long below_me, double cardS, Key &best,
                                                 unsigned long long &ccp) {
+    // a connected side of m members has at least m - 1 edges, and a
+    // disconnected side without cycles has fewer: most survivors that fail
+    // the CCP check fail this count, from per-chunk sums and no lookups
+    {
+        const uint32_t eH2 = edges.x & 0xffffu, eR2 = edges.x >> 16, nH = (uint32_t)popc32(H),
+                       nR = (uint32_t)popc32(RH);
+        for (uint32_t Lm = pend; Lm; Lm &= Lm - 1) {
+            const uint32_t t = (uint32_t)ctz32(Lm), r = ~t & 15u;
+            // low members named by t (left) and the others (right)
+            uint32_t el = eH2, er = eR2, il = 0, ir = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                el += ((t >> i) & 1u) ? 2u * ((edges.y >> (8 * i)) & 255u) : 0u;
+                er += ((r >> i) & 1u) ? 2u * ((edges.z >> (8 * i)) & 255u) : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = i + 1; j < 4; ++j) {
+                    const uint32_t adj = (edges.w >> (i * 4 + j)) & 1u;
+                    il += (adj && ((t >> i) & 1u) && ((t >> j) & 1u)) ? 2u : 0u;
+                    ir += (adj && ((r >> i) & 1u) && ((r >> j) & 1u)) ? 2u : 0u;
+                }
+            const uint32_t nl = nH + (uint32_t)popc32(t), nr = nR + (uint32_t)popc32(r);
+            if (el + il + 2u < 2u * nl || er + ir + 2u < 2u * nr) pend &= ~(1u << t);
+        }
+    }
     while (__ballot(pend != 0) != 0ull) {
         const uint32_t c = (uint32_t)popc32(pend);  // at most 16
         uint32_t before = 0;
@@ -1188,8 +1248,10 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
             cfill -= 64u;
             wave_sync_lds();
             uint32_t pend, H, RH, low4;
-            chunk_pass1(L, W, ce, pend, H, RH, low4);
-            place_survivors<CM>(L, M, S, A, k, pend, H, RH, low4, sv, fill, vfill, lane, below_me, cardS, best, ccp);
+            uint4 edges;
+            chunk_pass1(L, W, ce, pend, H, RH, low4, edges);
+            place_survivors<CM>(L, M, S, A, k, pend, H, RH, low4, edges, sv, fill, vfill, lane, below_me, cardS, best,
+                                ccp);
         }
     }
     if (kChunkTables) {
@@ -1197,8 +1259,10 @@ __device__ __forceinline__ void eval_chunks(const LdsGraph &L, const MemoPtrs &M
             const uint2 ce = lane < cfill ? cb[lane] : make_uint2(0u, 1u);  // an empty chunk: no candidate
             wave_sync_lds();
             uint32_t pend = 0, H = 0, RH = 0, low4 = 0;
-            if (lane < cfill) chunk_pass1(L, W, ce, pend, H, RH, low4);
-            place_survivors<CM>(L, M, S, A, k, pend, H, RH, low4, sv, fill, vfill, lane, below_me, cardS, best, ccp);
+            uint4 edges = make_uint4(0u, 0u, 0u, 0u);
+            if (lane < cfill) chunk_pass1(L, W, ce, pend, H, RH, low4, edges);
+            place_survivors<CM>(L, M, S, A, k, pend, H, RH, low4, edges, sv, fill, vfill, lane, below_me, cardS, best,
+                                ccp);
         }
         if (fill != 0u) {
             const uint2 e = lane < fill ? sv[lane] : make_uint2(0u, 0u);
