@@ -38,7 +38,7 @@ constexpr uint64_t kTreeSplitMaxCand = 4096;
 #define MPDP_HEAVY_CHUNKS 512
 #endif
 constexpr uint32_t kHeavyChunks = MPDP_HEAVY_CHUNKS;   // above this many 16-candidate chunks a set is heavy
-constexpr int kHeavyBlock = 1024;        // threads per heavy set
+constexpr int kHeavyBlock = 512;         // threads per heavy set
 constexpr uint32_t kMaxGrid = 8192; // workgroups per launch (grid-stride beyond)
 constexpr uint32_t kGeneralGrid = 1024;  // workgroups of a block-based level's light sets
 

@@ -159,7 +159,7 @@ struct HeavyPart {
     double card;
     double pad;
 };
-constexpr uint32_t kHeavyGrid = 512;  // workgroups of the heavy-set kernel (two per CU)
+constexpr uint32_t kHeavyGrid = 768;  // workgroups of the heavy-set kernel (three per CU)
 
 // Workgroups per heavy set: one while a level has at least one heavy set
 // per workgroup, else as many as share the grid evenly.

@@ -170,15 +170,15 @@ __global__ __launch_bounds__(kBlock) void k_eval_general(const DevGraph *g, uint
     }
 }
 
-// Alg. 3, heavy sets: one 1024-thread workgroup per set, or, when a level
+// Alg. 3, heavy sets: one 512-thread workgroup per set, or, when a level
 // has fewer heavy sets than workgroups (the top levels of a large cyclic
 // query: one set of all relations, then n, ...), `parts` workgroups per
-// set, each taking every parts-th run of 1024 candidate chunks; their keys
+// set, each taking every parts-th run of 512 candidate chunks; their keys
 // then go to HeavyPart records for k_heavy_reduce.  Wave 0 of each
-// workgroup finds the blocks, all 16 waves share the candidate chunks, and
+// workgroup finds the blocks, all 8 waves share the candidate chunks, and
 // the plan keys are reduced through LDS.
 template <int CM>
-__global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_eval_heavy(const DevGraph *g, uint32_t k, const uint32_t *heavy,
+__global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_eval_heavy(const DevGraph *g, uint32_t k, const uint32_t *heavy,
                                                             Counters *cnt, MemoPtrs M, HeavyPart *partrec) {
     constexpr int kHW = kHeavyBlock / 64;
     __shared__ __align__(16) LdsGraph L;
