@@ -11,7 +11,9 @@ Workloads (generators in paper_2202_13511_amd.workloads):
   star25      hub + 24 leaves, seeds 0..15, C_out and PG-like
   snowflake25 depth 3, fanout U{2..4}, seeds 0..63, C_out and PG-like
   clique18    seeds 0..31, C_out and PG-like
-  cycle       ring of U{20..30} + U{5..15} chords, seeds 0..31, C_out
+  cycle       ring of U{20..30} + U{5..15} chords, seeds 0..31, C_out; and
+              the seeds of 20-23 relations also under PG-like (its Alg. 3
+              path through the heavy-set kernel on sparse blocks)
 
 Every query is solved whole.  For the cyclic queries of 27 or more
 relations (whose whole solution takes the oracle from minutes to hours) the
@@ -54,6 +56,7 @@ def spec_list():
     specs += [("snowflake", 25, s, cm) for cm in (0, 1) for s in range(64)]
     specs += [("clique", 18, s, cm) for cm in (0, 1) for s in range(32)]
     specs += [("cycle_chords", None, s, 0) for s in range(32)]
+    specs += [("cycle_chords", None, s, 1) for s in range(32) if make_query("cycle_chords", None, s).n <= 23]
     specs += [("cycle_sub", None, s, 0) for s in range(32) if make_query("cycle_chords", None, s).n >= SUB_MIN_N]
     return specs
 
