@@ -616,6 +616,186 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
     eval_tree_sets<CM, 1, kPairBatch>(L, M, &S, &bsum, k, off_k, cost_km1, card_km1);
 }
 
+// Alg. 2 when the join tree, rooted at relation 0, has depth one: every
+// other relation is a leaf on relation 0 (a star around relation 0).  Every
+// connected set of two or more relations then holds relation 0 as its
+// smallest member, and the edge (0, m) of each other member m gives the
+// pair ({m}, S - {m}); so no subtree lookups, no topmost member to skip, and
+// every pair splits off one relation whose cost and card come from LDS.
+// card(S) is tree_card_n's product with its conditions settled: each member
+// ascending multiplies its card, then its selectivity to relation 0 (1.0
+// for relation 0 itself), and no member has another smaller neighbour.
+// Under C_out a batch's keys are reduced without per-pair branches: the
+// smallest cost of the batch and the running best first, then the smallest
+// left set among the pairs that reach it, which is key_less's order (a
+// connected set has at least one pair, so the running best's +inf start
+// never survives).  Pairs go in batches of kPairBatch (members 1 .. k - 1);
+// only the last batch of a set has slots past its last member.
+struct FlatBest {
+    double c;    // C_out: running smallest cost (+inf before the first pair)
+    uint32_t l;  // C_out: smallest left set at that cost
+    Key key;     // PG-like: running best key
+};
+
+template <int CM, int R, int kPairBatch, bool kFull, bool kUnfused>
+__device__ __forceinline__ void flat_batch(const LdsGraph &L, const uint32_t *S, const uint32_t *bsum,
+                                           uint32_t p0, uint32_t np, const double *cardS,
+                                           const double *__restrict__ cost_km1,
+                                           const double *__restrict__ card_km1, uint32_t *pa, uint32_t *pb,
+                                           uint32_t *T, FlatBest *best, const TreeSink &sink, uint32_t k) {
+    int mv[R][kPairBatch];
+    uint32_t rk[R][kPairBatch], ba[R][kPairBatch], bb[R][kPairBatch];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            const uint32_t i = p0 + (uint32_t)u + 1u;  // member index; slots past k read valid rows
+            const int m = ctz32(T[r] | 0x80000000u);
+            T[r] &= T[r] - 1;
+            mv[r][u] = m;
+            bb[r][u] = L.binom[m * 33 + i];
+            ba[r][u] = L.binom[m * 33 + i + 1];
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            const bool live = kFull || p0 + (uint32_t)u < np;  // uniform
+            pb[r] += bb[r][u];
+            rk[r][u] = live ? pa[r] + (bsum[r] - pb[r]) : 0u;  // a dead slot gathers entry 0
+            pa[r] += live ? ba[r][u] : 0u;
+        }
+    double cB[R][kPairBatch], kB[R][kPairBatch];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            cB[r][u] = cost_km1[rk[r][u]];
+            if (CM != MPDP_COST_COUT) kB[r][u] = card_km1[rk[r][u]];
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double c[kPairBatch];
+        uint32_t l[kPairBatch];
+        double mn = best[r].c;
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u) {
+            const bool live = kFull || p0 + (uint32_t)u < np;
+            const int m = mv[r][u] & 31;
+            const uint32_t A = 1u << m, B = S[r] ^ A;
+            const double cA = L.bcost[m];
+            const double base = cA + cB[r][u];
+            if (CM == MPDP_COST_COUT) {
+                c[u] = base + cardS[r];
+                l[u] = A < B ? A : B;
+                if (kUnfused) {
+                    if (live)
+                        sink.keys[(uint64_t)sink.slot[r] * k + p0 + (uint32_t)u + 1u] =
+                            PairKey{(unsigned long long)__double_as_longlong(c[u]), l[u], MPDP_OP_JOIN};
+                } else if (live) {
+                    mn = __builtin_fmin(mn, c[u]);
+                }
+            } else {
+                const double kA = L.card[m];
+                const double out = 0.01 * cardS[r];
+                const double hjA = ((base + 0.0125 * kB[r][u]) + 0.0025 * kA) + out;  // A outer, B hashed
+                const double nlA = (base + (0.0025 * kA) * kB[r][u]) + out;
+                const double hjB = ((base + 0.0125 * kA) + 0.0025 * kB[r][u]) + out;  // B outer, A hashed
+                const double nlB = (base + (0.0025 * kB[r][u]) * kA) + out;
+                const bool hA = hjA <= nlA, hB = hjB <= nlB;
+                if (kUnfused) {
+                    Key one = worst_key();
+                    offer_if<CM>(true, one, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                    offer_if<CM>(true, one, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                    if (live) sink.keys[(uint64_t)sink.slot[r] * k + p0 + (uint32_t)u + 1u] = PairKey{one.c, one.l, one.op};
+                } else {
+                    offer_if<CM>(live, best[r].key, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                    offer_if<CM>(live, best[r].key, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                }
+            }
+        }
+        if (CM == MPDP_COST_COUT && !kUnfused) {
+            uint32_t nl = best[r].c == mn ? best[r].l : ~0u;
+#pragma unroll
+            for (int u = 0; u < kPairBatch; ++u) {
+                const bool live = kFull || p0 + (uint32_t)u < np;
+                if (live) nl = min(nl, c[u] == mn ? l[u] : ~0u);
+            }
+            best[r].c = mn;
+            best[r].l = nl;
+        }
+    }
+}
+
+template <int CM, int R, int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false>
+__device__ __forceinline__ void eval_flat_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *S,
+                                               const uint32_t *bsum, uint32_t k, uint64_t off_k,
+                                               const double *__restrict__ cost_km1,
+                                               const double *__restrict__ card_km1,
+                                               const TreeSink &sink = TreeSink{}) {
+    constexpr int kCB = MPDP_TREE_CARD_BATCH;
+    double cardS[R];
+    {
+        double c[R];
+        uint32_t T[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) { c[r] = 1.0; T[r] = S[r]; }
+        for (uint32_t i0 = 0; i0 < k; i0 += kCB) {
+            double2 cs[R][kCB];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < kCB; ++u) {
+                    const int v = ctz32(T[r] | 0x80000000u);
+                    T[r] &= T[r] - 1;
+                    cs[r][u] = *reinterpret_cast<const double2 *>(L.csel[v]);
+                }
+#pragma unroll
+            for (int u = 0; u < kCB; ++u)
+                if (i0 + (uint32_t)u < k)  // uniform
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        c[r] = c[r] * cs[r][u].x;
+                        c[r] = c[r] * cs[r][u].y;
+                    }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) cardS[r] = c[r] < 1.0 ? 1.0 : c[r];
+    }
+    // relation 0 is member 0: C(0, 0) = 1 goes to pb, C(0, 1) = 0 to pa
+    uint32_t pa[R], pb[R], T[R];
+    FlatBest best[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        pa[r] = 0;
+        pb[r] = 1;
+        T[r] = S[r] & ~1u;
+        best[r].c = __builtin_inf();
+        best[r].l = ~0u;
+        best[r].key = worst_key();
+        if (kUnfused) sink.keys[(uint64_t)sink.slot[r] * k] = PairKey{~0ull, ~0u, ~0u};  // member 0 has no pair
+    }
+    const uint32_t np = k - 1;
+    uint32_t p0 = 0;
+    for (; p0 + kPairBatch <= np; p0 += kPairBatch)
+        flat_batch<CM, R, kPairBatch, true, kUnfused>(L, S, bsum, p0, np, cardS, cost_km1, card_km1, pa, pb, T, best,
+                                                      sink, k);
+    if (p0 < np)
+        flat_batch<CM, R, kPairBatch, false, kUnfused>(L, S, bsum, p0, np, cardS, cost_km1, card_km1, pa, pb, T,
+                                                       best, sink, k);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (kUnfused) {
+            sink.recs[sink.slot[r]] = PruneRec{pa[r], S[r], cardS[r]};
+        } else if (CM == MPDP_COST_COUT) {
+            store_best(M, off_k + pa[r], Key{(unsigned long long)__double_as_longlong(best[r].c), best[r].l,
+                                             MPDP_OP_JOIN}, cardS[r]);
+        } else {
+            store_best(M, off_k + pa[r], best[r].key, cardS[r]);
+        }
+    }
+}
+
 // eval_tree_set with the pairs of S spread over a group of P lanes (P
 // divides 64, groups are P consecutive lanes, all active together): lane
 // `sub` costs members sub, sub + P, ... (at most 32 / P of them, every
@@ -1356,6 +1536,18 @@ __device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoP
 // Returns the number of connected sets it found (uniform across the wave).
 // Outputs of the unfused-prune ablation (see TreeSink): the pair keys, the
 // set records and the counter that hands out their slots.
+// The set evaluation of a tree level: the depth-one form or the general one.
+template <int CM, int R, int kPairBatch, bool kUnfused, bool kFlat>
+__device__ __forceinline__ void eval_level_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *S,
+                                                const uint32_t *bsum, uint32_t k, uint64_t off_k,
+                                                const double *__restrict__ cost_km1,
+                                                const double *__restrict__ card_km1, const TreeSink &sink) {
+    if (kFlat)
+        eval_flat_sets<CM, R, kPairBatch, kUnfused>(L, M, S, bsum, k, off_k, cost_km1, card_km1, sink);
+    else
+        eval_tree_sets<CM, R, kPairBatch, kUnfused>(L, M, S, bsum, k, off_k, cost_km1, card_km1, sink);
+}
+
 struct UnfusedOut {
     PairKey *keys;
     PruneRec *recs;
@@ -1370,7 +1562,7 @@ __device__ __forceinline__ uint32_t take_slots(uint32_t *slots, uint32_t count, 
 }
 
 template <int CM, int kTreeChunk, bool kCompact = true, int kRingN = kRing, int kTreeSetsPerLane = 1,
-          int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false>
+          int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false, bool kFlat = false>
 __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
                                     uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *ring,
                                     uint32_t *ring_bsum, uint32_t lane,
@@ -1417,7 +1609,9 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         if (!kCompact) {  // ablation: each lane evaluates the sets it kept, lanes diverge
 #pragma unroll
             for (int j = 0; j < kTreeChunk; ++j)
-                if (keep & (1u << j)) eval_tree_set<CM, kPairBatch>(L, M, sets[j], bsums[j], k, off_k, cost_km1, card_km1);
+                if (keep & (1u << j))
+                    eval_level_sets<CM, 1, kPairBatch, false, kFlat>(L, M, &sets[j], &bsums[j], k, off_k, cost_km1,
+                                                                      card_km1, sink);
             tail += total;
             head = tail;
             continue;
@@ -1440,8 +1634,8 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
                 r[j] = ring_bsum[(head + 64u * j + lane) % kRingN];
             }
             if (kUnfused) sink.slot[0] = take_slots(uo.slots, 64u, lane);
-            eval_tree_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused>(L, M, s, r, k, off_k, cost_km1, card_km1,
-                                                                       sink);
+            eval_level_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused, kFlat>(L, M, s, r, k, off_k, cost_km1,
+                                                                                card_km1, sink);
             head += 64u * kTreeSetsPerLane;
         }
         wave_sync_lds();
@@ -1449,14 +1643,14 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
     while (tail - head >= 64) {
         const uint32_t s = ring[(head + lane) % kRingN], r = ring_bsum[(head + lane) % kRingN];
         if (kUnfused) sink.slot[0] = take_slots(uo.slots, 64u, lane);
-        eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+        eval_level_sets<CM, 1, kPairBatch, kUnfused, kFlat>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
         head += 64;
     }
     if (tail != head) {
         if (kUnfused) sink.slot[0] = take_slots(uo.slots, tail - head, lane);
         if (lane < tail - head) {
             const uint32_t s = ring[(head + lane) % kRingN], r = ring_bsum[(head + lane) % kRingN];
-            eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+            eval_level_sets<CM, 1, kPairBatch, kUnfused, kFlat>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
         }
     }
     wave_sync_lds();

@@ -129,7 +129,9 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
     if (seen != full) return MPDP_ENOTCONNECTED;
     q.is_tree = (m == n - 1);
     g.is_tree = q.is_tree ? 1u : 0u;
-    // tree rooted at relation 0: parent bits and subtree sets, via BFS order
+    // tree rooted at relation 0: parent bits and subtree sets, via BFS order;
+    // flat when every other relation hangs on relation 0 (a star around it)
+    g.flat = 0u;
     if (q.is_tree) {
         int order[32], head = 0, tail = 0;
         int parent[32];
@@ -150,6 +152,7 @@ mpdp_status validate(uint32_t n, uint32_t m, const mpdp_edge *edges, const doubl
             L.pd[v][0] = parent[v] >= 0 ? (1u << parent[v]) : 0u;
         }
         for (int i = tail - 1; i > 0; --i) L.pd[parent[order[i]]][1] |= L.pd[order[i]][1];
+        g.flat = (n >= 2 && (L.adj[0] & full) == (full & ~1u)) ? 1u : 0u;
     }
     // selectivities of the edges (u, v), u < v, grouped by v, u ascending
     uint32_t at = 0;
@@ -259,9 +262,10 @@ constexpr size_t kGraphCacheSize = 32;  // recorded graphs kept per thread
 struct GraphKey {
     void *ws, *pin;
     uint32_t n, cost_model;
-    bool general;
+    bool general, flat;  // the level kernels recorded depend on both
     bool operator==(const GraphKey &o) const {
-        return ws == o.ws && pin == o.pin && n == o.n && cost_model == o.cost_model && general == o.general;
+        return ws == o.ws && pin == o.pin && n == o.n && cost_model == o.cost_model && general == o.general &&
+               flat == o.flat;
     }
 };
 
@@ -411,10 +415,11 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
             if (general)
                 e = mpdp::launch_eval_general(dg, q.cost_model, k, nc, list, heavy, cnt, memo, parts, st);
             else if (unfused)  // ablation: evaluate writes every pair's key, prune reduces
-                e = mpdp::launch_level_tree_unfused(dg, q.cost_model, k, nc, cnt, memo, ukeys, urecs, st);
+                e = mpdp::launch_level_tree_unfused(dg, q.cost_model, k, nc, q.g.flat != 0, cnt, memo, ukeys, urecs,
+                                                    st);
             else  // tree joins: unrank, filter and evaluate in one kernel per level
                 e = mpdp::launch_level_tree(dg, q.cost_model, k, nc, (flags & MPDP_FLAG_ABLATE_NO_COMPACTION) == 0,
-                                            cnt, memo, st);
+                                            q.g.flat != 0, cnt, memo, st);
             if (e == hipSuccess && timing) e = hipEventRecord(ev.ev[4 * k - 6], st);
         }
         if (e == hipSuccess) e = mpdp::launch_extract(dg, n, memo, dplan, droot, cnt, st);
@@ -428,7 +433,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
         // replay the sequence recorded once for this workspace, staging
         // buffer and shape (the upload reads the staging buffer at replay)
         hipGraphExec_t exec = nullptr;
-        HIPCHK(cached_graph(GraphKey{d_ws, pin, n, (uint32_t)q.cost_model, general}, enqueue, exec));
+        HIPCHK(cached_graph(GraphKey{d_ws, pin, n, (uint32_t)q.cost_model, general, q.g.flat != 0}, enqueue, exec));
         HIPCHK(hipGraphLaunch(exec, s));
     } else {
         HIPCHK(enqueue(s));

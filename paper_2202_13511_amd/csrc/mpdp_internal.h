@@ -47,7 +47,9 @@ static_assert(sizeof(LdsImage) % 16 == 0, "LdsImage is copied in 16-byte units")
 struct DevGraph {
     LdsImage lds;
     uint32_t n, m, is_tree, cost_model;
-    uint32_t ablate, pad[3];             // kAblateDpsub: every connected set is one block (DPSUB's enumeration)
+    uint32_t ablate;                     // kAblateDpsub: every connected set is one block (DPSUB's enumeration)
+    uint32_t flat;                       // tree joins whose tree, rooted at relation 0, has depth one
+    uint32_t pad[2];
 };
 
 // Memo, level-compact: the entry of a relation set S sits at
@@ -134,8 +136,8 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
                          hipStream_t s);
 constexpr uint32_t kAblateDpsub = 1u;
 
-hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, Counters *cnt,
-                             MemoPtrs memo, hipStream_t s);
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, bool flat,
+                             Counters *cnt, MemoPtrs memo, hipStream_t s);
 
 // Unfused-prune ablation of a tree level (measurement only): the evaluate
 // kernel writes the key of every pair of every connected set (16 bytes,
@@ -150,8 +152,9 @@ struct PairKey {
     unsigned long long c;
     uint32_t l, op;
 };
-hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
-                                     MemoPtrs memo, PairKey *pair_keys, PruneRec *set_recs, hipStream_t s);
+hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool flat,
+                                     Counters *cnt, MemoPtrs memo, PairKey *pair_keys, PruneRec *set_recs,
+                                     hipStream_t s);
 // Key and card of one part of a heavy set split over several workgroups.
 struct HeavyPart {
     unsigned long long c;

@@ -62,7 +62,7 @@ __device__ __forceinline__ void wave_ranges(uint64_t nw, uint64_t &w0, uint64_t 
 // same-popcount successor), appends the connected sets to its LDS ring in
 // rank order, and evaluates 64 of them at a time, one per lane, so no lane
 // idles on a disconnected candidate.
-template <int CM, int kTreeChunk, bool kCompact>
+template <int CM, int kTreeChunk, bool kCompact, bool kFlat>
 __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32_t k, uint64_t ncand,
                                                        Counters *cnt, MemoPtrs M) {
     // the LDS image up to the first 32 selectivities: a tree join reads no
@@ -76,7 +76,8 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     const uint64_t per_wave = 64ull * kTreeChunk;
     uint64_t w0, ws, we;
     wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
-    const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact, kTreeRing, tree_sets_per_lane<CM>()>(
+    const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact, kTreeRing, tree_sets_per_lane<CM>(),
+                                           MPDP_TREE_PAIR_BATCH, false, kFlat>(
         L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_bsum_all[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
 // Unfused-prune ablation of a tree level (measurement only): the same walk
 // and pair costs, but every pair's key is written out (Section 5 before the
 // fusion of prune into evaluate) for k_prune.
-template <int CM, int kTreeChunk>
+template <int CM, int kTreeChunk, bool kFlat>
 __global__ __launch_bounds__(kBlock) void k_level_tree_unfused(const DevGraph *g, uint32_t k, uint64_t ncand,
                                                                Counters *cnt, MemoPtrs M, PairKey *keys,
                                                                PruneRec *recs) {
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_level_tree_unfused(const DevGraph *g
     const uint64_t per_wave = 64ull * kTreeChunk;
     uint64_t w0, ws, we;
     wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
-    const uint32_t found = level_tree_wave<CM, kTreeChunk, true, kTreeRing, 1, MPDP_TREE_PAIR_BATCH, true>(
+    const uint32_t found = level_tree_wave<CM, kTreeChunk, true, kTreeRing, 1, MPDP_TREE_PAIR_BATCH, true, kFlat>(
         L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_bsum_all[threadIdx.x >> 6], lane,
         UnfusedOut{keys, recs, &cnt->prune_slots[k]});
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
@@ -282,8 +283,8 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, Counters *cnt,
-                             MemoPtrs memo, hipStream_t s) {
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, bool flat,
+                             Counters *cnt, MemoPtrs memo, hipStream_t s) {
     // Fewer consecutive ranks per lane on small levels, so that even they
     // spread over some thousands of waves; a persistent-sized grid on large
     // ones, so each workgroup stages the query information once.
@@ -308,12 +309,17 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
+#define MPDP_LEVEL_TREE_F(CMV, CH, CP)                                                                  \
+    do {                                                                                                \
+        if (flat)                                                                                       \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, CP, true>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, CP, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+    } while (0)
 #define MPDP_LEVEL_TREE(CMV, CH)                                                                        \
     do {                                                                                                \
-        if (compact)                                                                                    \
-            hipLaunchKernelGGL((k_level_tree<CMV, CH, true>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
-        else                                                                                            \
-            hipLaunchKernelGGL((k_level_tree<CMV, CH, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+        if (compact) MPDP_LEVEL_TREE_F(CMV, CH, true);                                                  \
+        else MPDP_LEVEL_TREE_F(CMV, CH, false);                                                         \
     } while (0)
     if (cost_model == MPDP_COST_COUT) {
         if (chunk == 8) MPDP_LEVEL_TREE(MPDP_COST_COUT, 8);
@@ -326,19 +332,27 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
         else MPDP_LEVEL_TREE(MPDP_COST_PGLIKE, 1);
     }
 #undef MPDP_LEVEL_TREE
+#undef MPDP_LEVEL_TREE_F
     return hipGetLastError();
 }
 
-hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, Counters *cnt,
-                                     MemoPtrs memo, PairKey *keys, PruneRec *recs, hipStream_t s) {
+hipError_t launch_level_tree_unfused(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool flat,
+                                     Counters *cnt, MemoPtrs memo, PairKey *keys, PruneRec *recs, hipStream_t s) {
     // the launch shape of the fused kernel on the same level (chunk and grid)
     constexpr uint64_t kWantWaves = 1024;
     const int chunk = ncand >= 64ull * 4 * kWantWaves ? 4 : (ncand >= 64ull * 2 * kWantWaves ? 2 : 1);
     const uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
-#define MPDP_UNFUSED(CMV, CH) \
-    hipLaunchKernelGGL((k_level_tree_unfused<CMV, CH>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo, keys, recs)
+#define MPDP_UNFUSED(CMV, CH)                                                                                    \
+    do {                                                                                                         \
+        if (flat)                                                                                                \
+            hipLaunchKernelGGL((k_level_tree_unfused<CMV, CH, true>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, \
+                               cnt, memo, keys, recs);                                                           \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_level_tree_unfused<CMV, CH, false>), dim3(grid), dim3(kBlock), 0, s, g, k,      \
+                               ncand, cnt, memo, keys, recs);                                                    \
+    } while (0)
     if (cost_model == MPDP_COST_COUT) {
         if (chunk == 4) MPDP_UNFUSED(MPDP_COST_COUT, 4);
         else if (chunk == 2) MPDP_UNFUSED(MPDP_COST_COUT, 2);

@@ -150,13 +150,16 @@ def test_widest_bitmap_chain32(cm):
 def test_recorded_sequence_replays():
     """Queries of up to 20 relations replay a launch sequence recorded once
     per workspace and shape: replays with new data, interleaved with other
-    shapes, eager torch work and synchronizations, each match the oracle."""
+    shapes, eager torch work and synchronizations, each match the oracle.
+    A star and a chain of 12 relations share a workspace, model and size but
+    not their level kernels (the star's tree has depth one from relation 0),
+    so each must get its own recording."""
     import torch
     ws = {n: mpdp.workspace(n, 1, "cuda") for n in (12, 14)}
     refs = {}
     for rnd in range(4):
         for cm in (mpdp.MPDP_COST_COUT, mpdp.MPDP_COST_PGLIKE):
-            for q in (W.star(12, rnd), W.snowflake(14, rnd), W.cycle_chords(rnd, n=12, chords=3),
+            for q in (W.star(12, rnd), W.chain(12, rnd), W.snowflake(14, rnd), W.cycle_chords(rnd, n=12, chords=3),
                       W.random_connected(14, rnd, 0.3)):
                 key = (q.name, cm)
                 if key not in refs:
