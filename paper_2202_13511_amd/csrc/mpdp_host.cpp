@@ -418,7 +418,7 @@ mpdp_status run(const Query &q, void *d_ws, size_t ws_bytes, hipStream_t s, uint
                 e = mpdp::launch_level_tree_unfused(dg, q.cost_model, k, nc, q.g.flat != 0, cnt, memo, ukeys, urecs,
                                                     st);
             else  // tree joins: unrank, filter and evaluate in one kernel per level
-                e = mpdp::launch_level_tree(dg, q.cost_model, k, nc, (flags & MPDP_FLAG_ABLATE_NO_COMPACTION) == 0,
+                e = mpdp::launch_level_tree(dg, q.cost_model, n, k, nc, (flags & MPDP_FLAG_ABLATE_NO_COMPACTION) == 0,
                                             q.g.flat != 0, cnt, memo, st);
             if (e == hipSuccess && timing) e = hipEventRecord(ev.ev[4 * k - 6], st);
         }

@@ -136,8 +136,8 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
                          hipStream_t s);
 constexpr uint32_t kAblateDpsub = 1u;
 
-hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, bool flat,
-                             Counters *cnt, MemoPtrs memo, hipStream_t s);
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t n, uint32_t k, uint64_t ncand, bool compact,
+                             bool flat, Counters *cnt, MemoPtrs memo, hipStream_t s);
 
 // Unfused-prune ablation of a tree level (measurement only): the evaluate
 // kernel writes the key of every pair of every connected set (16 bytes,

@@ -82,6 +82,29 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
 
+// One level of a depth-one tree (a star around relation 0): the connected
+// sets {0} + T are enumerated directly by the colex rank of T among the
+// (k - 1)-subsets of relations 1 .. n - 1 (no filter); a wave's ranges
+// pass through an LDS block so that neighbouring lanes cost neighbouring
+// sets.
+template <int CM, int kTreeChunk>
+__global__ __launch_bounds__(kBlock) void k_level_flat(const DevGraph *g, uint32_t k, uint64_t nsets, Counters *cnt,
+                                                       MemoPtrs M) {
+    __shared__ __align__(16) unsigned char lds_tree[kTreeLdsBytes];
+    __shared__ uint32_t blk_set[kWaves][flat_block_words(kTreeChunk)];
+    __shared__ uint32_t blk_bsum[kWaves][flat_block_words(kTreeChunk)];
+    stage_graph_prefix(g, lds_tree, kTreeLdsBytes);
+    const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t per_wave = 64ull * kTreeChunk;
+    uint64_t w0, ws, we;
+    wave_ranges((nsets + per_wave - 1) / per_wave, w0, ws, we);
+    constexpr int R = tree_sets_per_lane<CM>() < kTreeChunk ? tree_sets_per_lane<CM>() : kTreeChunk;
+    const uint32_t found = level_flat_wave<CM, kTreeChunk, R>(L, M, (int)g->n, k, nsets, w0, ws, we,
+                                                              blk_set[threadIdx.x >> 6], blk_bsum[threadIdx.x >> 6], lane);
+    if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
+}
+
 // Unfused-prune ablation of a tree level (measurement only): the same walk
 // and pair costs, but every pair's key is written out (Section 5 before the
 // fusion of prune into evaluate) for k_prune.
@@ -283,8 +306,8 @@ hipError_t launch_filter(const DevGraph *g, uint32_t k, uint64_t ncand, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint64_t ncand, bool compact, bool flat,
-                             Counters *cnt, MemoPtrs memo, hipStream_t s) {
+hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t n, uint32_t k, uint64_t ncand, bool compact,
+                             bool flat, Counters *cnt, MemoPtrs memo, hipStream_t s) {
     // Fewer consecutive ranks per lane on small levels, so that even they
     // spread over some thousands of waves; a persistent-sized grid on large
     // ones, so each workgroup stages the query information once.
@@ -301,6 +324,30 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
                                memo);
         return hipGetLastError();
     }
+    if (compact && flat) {
+        // a depth-one tree: its C(n - 1, k - 1) connected sets directly
+        const uint64_t nsets = ncand * k / n;
+        const int chunk = (cost_model == MPDP_COST_COUT && nsets >= 64ull * 8 * kWantWaves)
+                              ? 8
+                              : (nsets >= 64ull * 4 * kWantWaves ? 4 : (nsets >= 64ull * 2 * kWantWaves ? 2 : 1));
+        const uint64_t blocks = (nsets + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
+        const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
+        const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
+#define MPDP_LEVEL_FLAT(CMV, CH) \
+    hipLaunchKernelGGL((k_level_flat<CMV, CH>), dim3(grid), dim3(kBlock), 0, s, g, k, nsets, cnt, memo)
+        if (cost_model == MPDP_COST_COUT) {
+            if (chunk == 8) MPDP_LEVEL_FLAT(MPDP_COST_COUT, 8);
+            else if (chunk == 4) MPDP_LEVEL_FLAT(MPDP_COST_COUT, 4);
+            else if (chunk == 2) MPDP_LEVEL_FLAT(MPDP_COST_COUT, 2);
+            else MPDP_LEVEL_FLAT(MPDP_COST_COUT, 1);
+        } else {
+            if (chunk == 4) MPDP_LEVEL_FLAT(MPDP_COST_PGLIKE, 4);
+            else if (chunk == 2) MPDP_LEVEL_FLAT(MPDP_COST_PGLIKE, 2);
+            else MPDP_LEVEL_FLAT(MPDP_COST_PGLIKE, 1);
+        }
+#undef MPDP_LEVEL_FLAT
+        return hipGetLastError();
+    }
     // eight ranks per lane only under C_out: PG-like keeps more registers
     // per set live and measured slower with them
     const int chunk = (cost_model == MPDP_COST_COUT && ncand >= 64ull * 8 * kWantWaves)
@@ -309,17 +356,16 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
     uint64_t blocks = (ncand + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
     const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
     const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
-#define MPDP_LEVEL_TREE_F(CMV, CH, CP)                                                                  \
-    do {                                                                                                \
-        if (flat)                                                                                       \
-            hipLaunchKernelGGL((k_level_tree<CMV, CH, CP, true>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
-        else                                                                                            \
-            hipLaunchKernelGGL((k_level_tree<CMV, CH, CP, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
-    } while (0)
+    // (a compacted depth-one level went to k_level_flat above; without
+    // compaction, the ablation, it keeps the depth-one evaluation)
 #define MPDP_LEVEL_TREE(CMV, CH)                                                                        \
     do {                                                                                                \
-        if (compact) MPDP_LEVEL_TREE_F(CMV, CH, true);                                                  \
-        else MPDP_LEVEL_TREE_F(CMV, CH, false);                                                         \
+        if (compact)                                                                                    \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, true, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+        else if (flat)                                                                                  \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, false, true>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_level_tree<CMV, CH, false, false>), dim3(grid), dim3(kBlock), 0, s, g, k, ncand, cnt, memo); \
     } while (0)
     if (cost_model == MPDP_COST_COUT) {
         if (chunk == 8) MPDP_LEVEL_TREE(MPDP_COST_COUT, 8);
@@ -332,7 +378,6 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t k, uint
         else MPDP_LEVEL_TREE(MPDP_COST_PGLIKE, 1);
     }
 #undef MPDP_LEVEL_TREE
-#undef MPDP_LEVEL_TREE_F
     return hipGetLastError();
 }
 
