@@ -58,6 +58,29 @@ static_assert(kTreeRing >= 64 * kTreeSetsMax - 1 + 64 * kTreeChunkMax, "ring too
 // members per batch of the tree pair loop (gathers in flight per lane; the
 // batched kernel, which keeps much more state live, takes three) and of the
 // card(S) pass (LDS reads in flight)
+// depth-one tree levels (k_level_flat): sets per lane and grid caps.  On
+// a 25-relation star (ms per query) the C_out cap of 256 / 384 / 512 / 768 /
+// 1024 workgroups gave 0.84 / 0.78 / 0.78 / 0.83 / 0.87, and the PG-like
+// cap of 512 / 768 / 1024 gave 1.14 / 1.12 / 1.20; four C_out sets per lane,
+// or two PG-like ones, gained nothing
+#ifndef MPDP_FLAT_SETS_PER_LANE_COUT
+#define MPDP_FLAT_SETS_PER_LANE_COUT 2
+#endif
+#ifndef MPDP_FLAT_SETS_PER_LANE_PG
+#define MPDP_FLAT_SETS_PER_LANE_PG 1
+#endif
+template <int CM>
+constexpr int flat_sets_per_lane() {
+    return CM == MPDP_COST_COUT ? MPDP_FLAT_SETS_PER_LANE_COUT : MPDP_FLAT_SETS_PER_LANE_PG;
+}
+#ifndef MPDP_FLAT_GRID_COUT
+#define MPDP_FLAT_GRID_COUT 512
+#endif
+#ifndef MPDP_FLAT_GRID
+#define MPDP_FLAT_GRID 768
+#endif
+constexpr uint32_t kFlatGridCout = MPDP_FLAT_GRID_COUT;
+constexpr uint32_t kFlatGrid = MPDP_FLAT_GRID;
 #ifndef MPDP_TREE_PAIR_BATCH
 #define MPDP_TREE_PAIR_BATCH 4
 #endif

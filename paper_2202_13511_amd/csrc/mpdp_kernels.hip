@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_level_flat(const DevGraph *g, uint32
     const uint64_t per_wave = 64ull * kTreeChunk;
     uint64_t w0, ws, we;
     wave_ranges((nsets + per_wave - 1) / per_wave, w0, ws, we);
-    constexpr int R = tree_sets_per_lane<CM>() < kTreeChunk ? tree_sets_per_lane<CM>() : kTreeChunk;
+    constexpr int R = flat_sets_per_lane<CM>() < kTreeChunk ? flat_sets_per_lane<CM>() : kTreeChunk;
     const uint32_t found = level_flat_wave<CM, kTreeChunk, R>(L, M, (int)g->n, k, nsets, w0, ws, we,
                                                               blk_set[threadIdx.x >> 6], blk_bsum[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
@@ -331,7 +331,7 @@ hipError_t launch_level_tree(const DevGraph *g, int cost_model, uint32_t n, uint
                               ? 8
                               : (nsets >= 64ull * 4 * kWantWaves ? 4 : (nsets >= 64ull * 2 * kWantWaves ? 2 : 1));
         const uint64_t blocks = (nsets + (uint64_t)kBlock * chunk - 1) / ((uint64_t)kBlock * chunk);
-        const uint32_t cap = cost_model == MPDP_COST_COUT ? kPersistGridCout : kPersistGrid;
+        const uint32_t cap = cost_model == MPDP_COST_COUT ? kFlatGridCout : kFlatGrid;
         const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
 #define MPDP_LEVEL_FLAT(CMV, CH) \
     hipLaunchKernelGGL((k_level_flat<CMV, CH>), dim3(grid), dim3(kBlock), 0, s, g, k, nsets, cnt, memo)
