@@ -210,7 +210,7 @@ def main() -> int:
         },
         "ms_per_step_with_events": dt_ev / args.steps * 1e3,
         "roofline": {
-            "kernel": "k_level_tree + k_level_tree_split <C_out>",
+            "kernel": "k_level_flat + k_level_tree_split <C_out>",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
