@@ -1631,18 +1631,6 @@ __device__ uint32_t level_flat_wave(const LdsGraph &L, const MemoPtrs &M, int n,
 // Returns the number of connected sets it found (uniform across the wave).
 // Outputs of the unfused-prune ablation (see TreeSink): the pair keys, the
 // set records and the counter that hands out their slots.
-// The set evaluation of a tree level: the depth-one form or the general one.
-template <int CM, int R, int kPairBatch, bool kUnfused, bool kFlat>
-__device__ __forceinline__ void eval_level_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *S,
-                                                const uint32_t *bsum, uint32_t k, uint64_t off_k,
-                                                const double *__restrict__ cost_km1,
-                                                const double *__restrict__ card_km1, const TreeSink &sink) {
-    if (kFlat)
-        eval_flat_sets<CM, R, kPairBatch, kUnfused>(L, M, S, bsum, k, off_k, cost_km1, card_km1, sink);
-    else
-        eval_tree_sets<CM, R, kPairBatch, kUnfused>(L, M, S, bsum, k, off_k, cost_km1, card_km1, sink);
-}
-
 struct UnfusedOut {
     PairKey *keys;
     PruneRec *recs;
@@ -1704,9 +1692,12 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         if (!kCompact) {  // ablation: each lane evaluates the sets it kept, lanes diverge
 #pragma unroll
             for (int j = 0; j < kTreeChunk; ++j)
-                if (keep & (1u << j))
-                    eval_level_sets<CM, 1, kPairBatch, false, kFlat>(L, M, &sets[j], &bsums[j], k, off_k, cost_km1,
-                                                                      card_km1, sink);
+                if (keep & (1u << j)) {
+                    if constexpr (kFlat)
+                        eval_flat_sets<CM, 1, kPairBatch>(L, M, &sets[j], &bsums[j], k, off_k, cost_km1, card_km1);
+                    else
+                        eval_tree_set<CM, kPairBatch>(L, M, sets[j], bsums[j], k, off_k, cost_km1, card_km1);
+                }
             tail += total;
             head = tail;
             continue;
@@ -1729,8 +1720,12 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
                 r[j] = ring_bsum[(head + 64u * j + lane) % kRingN];
             }
             if (kUnfused) sink.slot[0] = take_slots(uo.slots, 64u, lane);
-            eval_level_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused, kFlat>(L, M, s, r, k, off_k, cost_km1,
-                                                                                card_km1, sink);
+            if constexpr (kFlat)
+                eval_flat_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused>(L, M, s, r, k, off_k, cost_km1, card_km1,
+                                                                           sink);
+            else
+                eval_tree_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused>(L, M, s, r, k, off_k, cost_km1, card_km1,
+                                                                           sink);
             head += 64u * kTreeSetsPerLane;
         }
         wave_sync_lds();
@@ -1738,14 +1733,20 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
     while (tail - head >= 64) {
         const uint32_t s = ring[(head + lane) % kRingN], r = ring_bsum[(head + lane) % kRingN];
         if (kUnfused) sink.slot[0] = take_slots(uo.slots, 64u, lane);
-        eval_level_sets<CM, 1, kPairBatch, kUnfused, kFlat>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+        if constexpr (kFlat)
+            eval_flat_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+        else
+            eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
         head += 64;
     }
     if (tail != head) {
         if (kUnfused) sink.slot[0] = take_slots(uo.slots, tail - head, lane);
         if (lane < tail - head) {
             const uint32_t s = ring[(head + lane) % kRingN], r = ring_bsum[(head + lane) % kRingN];
-            eval_level_sets<CM, 1, kPairBatch, kUnfused, kFlat>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+            if constexpr (kFlat)
+                eval_flat_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+            else
+                eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
         }
     }
     wave_sync_lds();
