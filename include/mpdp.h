@@ -97,7 +97,10 @@ typedef struct {
  *            every subset holding its lowest relation, CCP-checked) instead of
  *            Alg. 2/3's block-local ones; evaluated_pairs counts 2^|S| - 2 per set
  * NO_COMPACTION  tree joins: each lane evaluates the connected candidates it
- *            unranked instead of compacting them through the wave's LDS ring
+ *            unranked instead of compacting them through the wave's LDS ring;
+ *            a tree of depth one from relation 0 (a star around it), whose
+ *            connected sets are otherwise enumerated directly, is then
+ *            unranked and filtered over every k-subset as well
  * UNFUSED_PRUNE  tree joins: prune is not fused into evaluate (Section 5,
  *            "Enhancements"): the evaluate kernel writes the key of every
  *            pair to global memory and a separate prune kernel reduces each
