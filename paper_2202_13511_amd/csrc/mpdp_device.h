@@ -1553,48 +1553,48 @@ __device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoP
 // connected sets of k relations are {0} + T for the (k - 1)-subsets T of
 // relations 1 .. n - 1, so the wave walks the colex ranks of T' = T >> 1
 // among the (k - 1)-subsets of n - 1 relations: every rank is a connected
-// set, with nothing to filter.  A range is 64 * kTreeChunk ranks: each lane
-// unranks kTreeChunk consecutive ones (the first, then same-popcount
-// successors) into the wave's LDS block, and then evaluates the ranks
-// lane, 64 + lane, ..., R at a time, so that neighbouring lanes cost
-// neighbouring sets (their gathers and stores share lines).  The block has
-// one pad word per 8, which keeps both the writes (stride kTreeChunk) and
-// the reads (stride 1) free of bank conflicts.  Pascal's rule
-// C(t + 1, j + 1) = C(t, j + 1) + C(t, j) gives the sum eval_flat_sets
-// takes, bsum(S) = C(0, 0) + sum_j C(t'_j + 1, j + 1) = 1 + rank(T') +
-// bsum(T').  Returns the number of sets the wave evaluated (uniform).
+// set, with nothing to filter.  Every set of a level costs the same, so the
+// wave takes an equal share of the level, the ranks [r_begin, r_end), in
+// blocks of 64 * kTreeChunk: each lane unranks kTreeChunk consecutive ranks
+// (the first, then same-popcount successors) into the wave's LDS block, and
+// then evaluates the ranks lane, 64 + lane, ..., R at a time, so that
+// neighbouring lanes cost neighbouring sets (their gathers and stores share
+// lines).  The block has one pad word per 8, which keeps both the writes
+// (stride kTreeChunk) and the reads (stride 1) free of bank conflicts.  In
+// the last, partial block a group of R slots that is full on every lane
+// still goes R at a time; only the group that straddles the end goes one
+// slot at a time.  Pascal's rule C(t + 1, j + 1) = C(t, j + 1) + C(t, j)
+// gives the sum eval_flat_sets takes, bsum(S) = C(0, 0) +
+// sum_j C(t'_j + 1, j + 1) = 1 + rank(T') + bsum(T').
 constexpr __host__ __device__ int flat_block_words(int chunk) { return 64 * chunk + 64 * chunk / 8; }
 
 template <int CM, int kTreeChunk, int R>
-__device__ uint32_t level_flat_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t nsets,
-                                    uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *blk_set,
-                                    uint32_t *blk_bsum, uint32_t lane) {
+__device__ void level_flat_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t r_begin,
+                                uint64_t r_end, uint32_t *blk_set, uint32_t *blk_bsum, uint32_t lane) {
     static_assert(kTreeChunk % R == 0, "sets per lane come in groups of R");
     const uint64_t per_wave = 64ull * kTreeChunk;
     const uint64_t off_k = L.loff[k], off_km1 = L.loff[k - 1];
     const double *cost_km1 = M.cost + off_km1;
     const double *card_km1 = M.card + off_km1;
-    uint32_t found = 0;
-    for (uint64_t w = w0; w < wend; w += wstride) {
-        const uint64_t base = w * per_wave;
+    for (uint64_t base = r_begin; base < r_end; base += per_wave) {
         const uint64_t r0 = base + (uint64_t)lane * kTreeChunk;
         uint32_t bT = 0;
-        uint32_t Tp = r0 < nsets ? colex_unrank_b(L.binom, n - 1, (int)k - 1, (uint32_t)r0, bT) : 0u;
+        uint32_t Tp = r0 < r_end ? colex_unrank_b(L.binom, n - 1, (int)k - 1, (uint32_t)r0, bT) : 0u;
 #pragma unroll
         for (int j = 0; j < kTreeChunk; ++j) {
             const uint32_t e = lane * kTreeChunk + (uint32_t)j;  // element of the block
             blk_set[e + e / 8] = (Tp << 1) | 1u;
             blk_bsum[e + e / 8] = 1u + (uint32_t)(r0 + (uint64_t)j) + bT;
-            if (r0 + (uint64_t)j + 1 < nsets) {
+            if (r0 + (uint64_t)j + 1 < r_end) {
                 bT = next_bsum(Tp, bT);
                 Tp = next_subset(Tp);
             }
         }
         wave_sync_lds();
-        const uint64_t left = nsets - base;  // w < wend: some ranks remain
-        if (left >= per_wave) {
+        const uint64_t left = r_end - base;  // elements of this block in range (uniform)
 #pragma unroll
-            for (int j = 0; j < kTreeChunk; j += R) {
+        for (int j = 0; j < kTreeChunk; j += R) {
+            if ((uint64_t)(j + R) * 64u <= left) {  // the whole group, on every lane
                 uint32_t s[R], b[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -1603,22 +1603,19 @@ __device__ uint32_t level_flat_wave(const LdsGraph &L, const MemoPtrs &M, int n,
                     b[r] = blk_bsum[e + e / 8];
                 }
                 eval_flat_sets<CM, R>(L, M, s, b, k, off_k, cost_km1, card_km1);
-            }
-            found += (uint32_t)per_wave;
-        } else {  // the level's last range: elements past its end take nothing
+            } else if ((uint64_t)j * 64u < left) {  // the group that straddles the end
 #pragma unroll
-            for (int j = 0; j < kTreeChunk; ++j) {
-                const uint32_t e = (uint32_t)j * 64u + lane;
-                if (e < left) {
-                    const uint32_t s = blk_set[e + e / 8], b = blk_bsum[e + e / 8];
-                    eval_flat_sets<CM, 1>(L, M, &s, &b, k, off_k, cost_km1, card_km1);
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t e = (uint32_t)(j + r) * 64u + lane;
+                    if (e < left) {
+                        const uint32_t s1 = blk_set[e + e / 8], b1 = blk_bsum[e + e / 8];
+                        eval_flat_sets<CM, 1>(L, M, &s1, &b1, k, off_k, cost_km1, card_km1);
+                    }
                 }
             }
-            found += (uint32_t)left;
         }
         wave_sync_lds();
     }
-    return found;
 }
 
 // One wave's share of an Alg. 2 level (unrank, filter, evaluate, prune and

@@ -84,9 +84,10 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
 
 // One level of a depth-one tree (a star around relation 0): the connected
 // sets {0} + T are enumerated directly by the colex rank of T among the
-// (k - 1)-subsets of relations 1 .. n - 1 (no filter); a wave's ranges
-// pass through an LDS block so that neighbouring lanes cost neighbouring
-// sets.
+// (k - 1)-subsets of relations 1 .. n - 1 (no filter), and every wave takes
+// an equal contiguous share of them.  With the grid a multiple of 8, the
+// workgroups of one XCD (blockIdx mod 8) share one eighth of the level, so
+// each XCD's L2 sees one contiguous part of the slabs.
 template <int CM, int kTreeChunk>
 __global__ __launch_bounds__(kBlock) void k_level_flat(const DevGraph *g, uint32_t k, uint64_t nsets, Counters *cnt,
                                                        MemoPtrs M) {
@@ -96,13 +97,20 @@ __global__ __launch_bounds__(kBlock) void k_level_flat(const DevGraph *g, uint32
     stage_graph_prefix(g, lds_tree, kTreeLdsBytes);
     const LdsGraph &L = *reinterpret_cast<const LdsGraph *>(lds_tree);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t per_wave = 64ull * kTreeChunk;
-    uint64_t w0, ws, we;
-    wave_ranges((nsets + per_wave - 1) / per_wave, w0, ws, we);
+    uint64_t lo = 0, len = nsets, wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6),
+             waves = (uint64_t)gridDim.x * kWaves;
+    if ((gridDim.x & 7u) == 0) {
+        const uint64_t x = blockIdx.x & 7u;
+        lo = nsets * x / 8;
+        len = nsets * (x + 1) / 8 - lo;
+        wave = (uint64_t)(blockIdx.x >> 3) * kWaves + (threadIdx.x >> 6);
+        waves = (uint64_t)(gridDim.x >> 3) * kWaves;
+    }
+    const uint64_t r_begin = lo + len * wave / waves, r_end = lo + len * (wave + 1) / waves;
     constexpr int R = flat_sets_per_lane<CM>() < kTreeChunk ? flat_sets_per_lane<CM>() : kTreeChunk;
-    const uint32_t found = level_flat_wave<CM, kTreeChunk, R>(L, M, (int)g->n, k, nsets, w0, ws, we,
-                                                              blk_set[threadIdx.x >> 6], blk_bsum[threadIdx.x >> 6], lane);
-    if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
+    level_flat_wave<CM, kTreeChunk, R>(L, M, (int)g->n, k, r_begin, r_end, blk_set[threadIdx.x >> 6],
+                                       blk_bsum[threadIdx.x >> 6], lane);
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&cnt->level_count[k], (uint32_t)nsets);
 }
 
 // Unfused-prune ablation of a tree level (measurement only): the same walk
