@@ -1553,9 +1553,13 @@ __device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoP
 // connected sets of k relations are {0} + T for the (k - 1)-subsets T of
 // relations 1 .. n - 1, so the wave walks the colex ranks of T' = T >> 1
 // among the (k - 1)-subsets of n - 1 relations: every rank is a connected
-// set, with nothing to filter.  Every set of a level costs the same, so the
-// wave takes an equal share of the level, the ranks [r_begin, r_end), in
-// blocks of 64 * kTreeChunk: each lane unranks kTreeChunk consecutive ranks
+// set, with nothing to filter.  Every set of a level costs the same.  Of
+// the ranks [lo, lo + len) that its group of `waves` waves shares, a wave
+// takes the blocks of 64 * kTreeChunk ranks round-robin for as many full
+// rounds as fit (so that, at any time, the group works on one window of the
+// level and its gathers share the caches), then an equal part of what
+// remains, so that no wave idles while others finish a last block.  In a
+// block each lane unranks kTreeChunk consecutive ranks
 // (the first, then same-popcount successors) into the wave's LDS block, and
 // then evaluates the ranks lane, 64 + lane, ..., R at a time, so that
 // neighbouring lanes cost neighbouring sets (their gathers and stores share
@@ -1569,14 +1573,25 @@ __device__ __forceinline__ void eval_treelike_set(const LdsGraph &L, const MemoP
 constexpr __host__ __device__ int flat_block_words(int chunk) { return 64 * chunk + 64 * chunk / 8; }
 
 template <int CM, int kTreeChunk, int R>
-__device__ void level_flat_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t r_begin,
-                                uint64_t r_end, uint32_t *blk_set, uint32_t *blk_bsum, uint32_t lane) {
+__device__ void level_flat_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t lo, uint64_t len,
+                                uint64_t wave, uint64_t waves, uint32_t *blk_set, uint32_t *blk_bsum, uint32_t lane) {
     static_assert(kTreeChunk % R == 0, "sets per lane come in groups of R");
     const uint64_t per_wave = 64ull * kTreeChunk;
     const uint64_t off_k = L.loff[k], off_km1 = L.loff[k - 1];
     const double *cost_km1 = M.cost + off_km1;
     const double *card_km1 = M.card + off_km1;
-    for (uint64_t base = r_begin; base < r_end; base += per_wave) {
+    const uint64_t rounds = len / (waves * per_wave);
+    const uint64_t tail_lo = lo + rounds * waves * per_wave, tail_len = lo + len - tail_lo;
+    for (uint64_t it = 0; it <= rounds; ++it) {
+        uint64_t base, r_end;
+        if (it < rounds) {
+            base = lo + (it * waves + wave) * per_wave;
+            r_end = base + per_wave;
+        } else {
+            base = tail_lo + tail_len * wave / waves;
+            r_end = tail_lo + tail_len * (wave + 1) / waves;
+            if (base >= r_end) break;
+        }
         const uint64_t r0 = base + (uint64_t)lane * kTreeChunk;
         uint32_t bT = 0;
         uint32_t Tp = r0 < r_end ? colex_unrank_b(L.binom, n - 1, (int)k - 1, (uint32_t)r0, bT) : 0u;

@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
 
 // One level of a depth-one tree (a star around relation 0): the connected
 // sets {0} + T are enumerated directly by the colex rank of T among the
-// (k - 1)-subsets of relations 1 .. n - 1 (no filter), and every wave takes
-// an equal contiguous share of them.  With the grid a multiple of 8, the
+// (k - 1)-subsets of relations 1 .. n - 1 (no filter), shared evenly by the
+// waves (see level_flat_wave).  With the grid a multiple of 8, the
 // workgroups of one XCD (blockIdx mod 8) share one eighth of the level, so
 // each XCD's L2 sees one contiguous part of the slabs.
 template <int CM, int kTreeChunk>
@@ -106,9 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_level_flat(const DevGraph *g, uint32
         wave = (uint64_t)(blockIdx.x >> 3) * kWaves + (threadIdx.x >> 6);
         waves = (uint64_t)(gridDim.x >> 3) * kWaves;
     }
-    const uint64_t r_begin = lo + len * wave / waves, r_end = lo + len * (wave + 1) / waves;
     constexpr int R = flat_sets_per_lane<CM>() < kTreeChunk ? flat_sets_per_lane<CM>() : kTreeChunk;
-    level_flat_wave<CM, kTreeChunk, R>(L, M, (int)g->n, k, r_begin, r_end, blk_set[threadIdx.x >> 6],
+    level_flat_wave<CM, kTreeChunk, R>(L, M, (int)g->n, k, lo, len, wave, waves, blk_set[threadIdx.x >> 6],
                                        blk_bsum[threadIdx.x >> 6], lane);
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&cnt->level_count[k], (uint32_t)nsets);
 }
