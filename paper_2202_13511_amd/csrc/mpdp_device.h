@@ -446,7 +446,7 @@ struct TreeSink {
     uint32_t slot[2] = {0, 0};
 };
 
-template <int CM, int R, int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false>
+template <int CM, int R, int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false, bool kBatchKeys = false>
 __device__ __forceinline__ void eval_tree_sets(const LdsGraph &L, const MemoPtrs &M, const uint32_t *S,
                                                const uint32_t *bsum, uint32_t k, uint64_t off_k,
                                                const double *__restrict__ cost_km1,
@@ -459,10 +459,12 @@ __device__ __forceinline__ void eval_tree_sets(const LdsGraph &L, const MemoPtrs
     // C_out offers carry one operator, so the running best starts with it
     // and the operator never decides
     Key best[R];
+    double bc[R];  // kBatchKeys (C_out): running smallest cost, +inf before the first pair
     uint32_t pa[R], pb[R], T[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         best[r] = worst_key();
+        bc[r] = __builtin_inf();
         if (CM == MPDP_COST_COUT) best[r].op = MPDP_OP_JOIN;
         pa[r] = pb[r] = 0;
         T[r] = S[r];
@@ -559,6 +561,31 @@ __device__ __forceinline__ void eval_tree_sets(const LdsGraph &L, const MemoPtrs
                     if (CM != MPDP_COST_COUT) kA[r][u] = single ? L.card[m] : hA[r][u];
                 }
         }
+        if (CM == MPDP_COST_COUT && kBatchKeys && !kUnfused) {
+            // the batch's keys without per-pair branches: the smallest cost
+            // of the batch and the running best, then the smallest left set
+            // among the pairs that reach it (the key order); a slot without
+            // a pair costs +inf, and a connected set has at least one pair
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double c[kPairBatch];
+                uint32_t l[kPairBatch];
+                double mn = bc[r];
+#pragma unroll
+                for (int u = 0; u < kPairBatch; ++u) {
+                    const uint32_t A = Av[r][u], B = S[r] ^ A;
+                    c[u] = A != 0 ? (cA[r][u] + cB[r][u]) + cardS[r] : __builtin_inf();
+                    l[u] = A < B ? A : B;
+                    mn = __builtin_fmin(mn, c[u]);
+                }
+                uint32_t nl = bc[r] == mn ? best[r].l : ~0u;
+#pragma unroll
+                for (int u = 0; u < kPairBatch; ++u) nl = min(nl, c[u] == mn ? l[u] : ~0u);
+                bc[r] = mn;
+                best[r].l = nl;
+            }
+            continue;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -602,6 +629,7 @@ __device__ __forceinline__ void eval_tree_sets(const LdsGraph &L, const MemoPtrs
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        if (CM == MPDP_COST_COUT && kBatchKeys && !kUnfused) best[r].c = (unsigned long long)__double_as_longlong(bc[r]);
         if (kUnfused) sink.recs[sink.slot[r]] = PruneRec{pa[r], S[r], cardS[r]};
         else store_best(M, off_k + pa[r], best[r], cardS[r]);
     }
@@ -1657,7 +1685,8 @@ __device__ __forceinline__ uint32_t take_slots(uint32_t *slots, uint32_t count, 
 }
 
 template <int CM, int kTreeChunk, bool kCompact = true, int kRingN = kRing, int kTreeSetsPerLane = 1,
-          int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false, bool kFlat = false>
+          int kPairBatch = MPDP_TREE_PAIR_BATCH, bool kUnfused = false, bool kFlat = false,
+          bool kBatchKeys = false>
 __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n, uint32_t k, uint64_t ncand,
                                     uint64_t w0, uint64_t wstride, uint64_t wend, uint32_t *ring,
                                     uint32_t *ring_bsum, uint32_t lane,
@@ -1736,8 +1765,8 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
                 eval_flat_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused>(L, M, s, r, k, off_k, cost_km1, card_km1,
                                                                            sink);
             else
-                eval_tree_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused>(L, M, s, r, k, off_k, cost_km1, card_km1,
-                                                                           sink);
+                eval_tree_sets<CM, kTreeSetsPerLane, kPairBatch, kUnfused, kBatchKeys>(L, M, s, r, k, off_k, cost_km1,
+                                                                                       card_km1, sink);
             head += 64u * kTreeSetsPerLane;
         }
         wave_sync_lds();
@@ -1748,7 +1777,7 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
         if constexpr (kFlat)
             eval_flat_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
         else
-            eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+            eval_tree_sets<CM, 1, kPairBatch, kUnfused, kBatchKeys>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
         head += 64;
     }
     if (tail != head) {
@@ -1758,7 +1787,8 @@ __device__ uint32_t level_tree_wave(const LdsGraph &L, const MemoPtrs &M, int n,
             if constexpr (kFlat)
                 eval_flat_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
             else
-                eval_tree_sets<CM, 1, kPairBatch, kUnfused>(L, M, &s, &r, k, off_k, cost_km1, card_km1, sink);
+                eval_tree_sets<CM, 1, kPairBatch, kUnfused, kBatchKeys>(L, M, &s, &r, k, off_k, cost_km1, card_km1,
+                                                                        sink);
         }
     }
     wave_sync_lds();

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_level_tree(const DevGraph *g, uint32
     uint64_t w0, ws, we;
     wave_ranges((ncand + per_wave - 1) / per_wave, w0, ws, we);
     const uint32_t found = level_tree_wave<CM, kTreeChunk, kCompact, kTreeRing, tree_sets_per_lane<CM>(),
-                                           MPDP_TREE_PAIR_BATCH, false, kFlat>(
+                                           MPDP_TREE_PAIR_BATCH, false, kFlat, true>(
         L, M, (int)g->n, k, ncand, w0, ws, we, ring_all[threadIdx.x >> 6], ring_bsum_all[threadIdx.x >> 6], lane);
     if (lane == 0 && found) atomicAdd(&cnt->level_count[k], found);
 }
