@@ -35,7 +35,7 @@ def test_units_exact_step(cm):
     import torch
     qs = [with_base_costs(W.snowflake(14, 1), 1), with_base_costs(W.cycle_chords(3, n=13, chords=4), 2),
           with_base_costs(W.clique(9, 3), 3), with_base_costs(W.random_tree(18, 4), 4),
-          with_base_costs(W.chain(2, 5), 5)]
+          with_base_costs(W.chain(2, 5), 5), with_base_costs(W.star(12, 6), 6)]
     for q in qs:
         print(q.name, cm, flush=True)
         ws = mpdp.workspace(q.n, cm, "cuda")
