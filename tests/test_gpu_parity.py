@@ -147,6 +147,47 @@ def test_widest_bitmap_chain32(cm):
     assert res.stats["connected_sets"] == 32 * 33 // 2 - 32
 
 
+def bits(x):
+    return int(np.float64(x).view(np.uint64))
+
+
+@pytest.mark.parametrize("cm", CMS)
+def test_widest_star32(cm):
+    """A 32-relation star fills the bitmap on the depth-one path (levels of
+    up to C(31, 15) = 300 M connected sets).  Checked with what holds at any
+    size: the counts of connected sets and csg-cmp pairs; the plan recosts
+    to the root cost; every plan node of at most 16 relations equals the
+    oracle's root of its induced sub-query; and under C_out the root cost is
+    the closed form within rounding: every plan of a star joins one leaf at
+    a time onto the hub, so C_out sums the cardinalities of the growing
+    prefixes, and exchanging two neighbouring leaves shows that ascending
+    card(v) * sel(0, v) is an optimal order (the clamp at 1 is monotone)."""
+    q = W.star(32, 7)
+    res = mpdp.mpdp_optimize(q, cm)
+    assert res.stats["connected_sets"] == (1 << 31) - 1
+    assert res.stats["ccp_pairs"] == 31 * (1 << 30)
+    assert oracle.recost_plan(q, res.plan, cm) == res.cost
+    checked = 0
+    for nd in res.plan[32:]:
+        S = nd["relset"]
+        if bin(S).count("1") > 16:
+            continue
+        sub, rel = oracle.induced(q, S)
+        m = oracle.mpdp(sub, cm)
+        assert bits(nd["cost"]) == bits(m.root_cost) and bits(nd["card"]) == bits(m.card[m.full]), S
+        assert res.plan[nd["left"]]["relset"] == oracle.expand(rel, int(m.left[m.full])), S
+        assert nd["op"] == int(m.op[m.full]), S
+        checked += 1
+    assert checked == 15
+    if cm == mpdp.MPDP_COST_COUT:
+        f = sorted(float(q.card[v]) * float(q.sel[v - 1]) for v in range(1, 32))
+        prefix, total = float(q.card[0]), 0.0
+        for x in f:
+            prefix *= x
+            total += max(1.0, prefix)
+        assert abs(res.cost - total) <= 1e-12 * total, (res.cost, total)
+
+
 def test_recorded_sequence_replays():
     """Queries of up to 20 relations replay a launch sequence recorded once
     per workspace and shape: replays with new data, interleaved with other
