@@ -683,9 +683,9 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
 // never survives).  Pairs go in batches of kPairBatch (members 1 .. k - 1);
 // only the last batch of a set has slots past its last member.
 struct FlatBest {
-    double c;    // C_out: running smallest cost (+inf before the first pair)
-    uint32_t l;  // C_out: smallest left set at that cost
-    Key key;     // PG-like: running best key
+    double c;     // running smallest cost (+inf before the first pair)
+    uint32_t l;   // smallest left set at that cost
+    uint32_t op;  // its operator (PG-like)
 };
 
 template <int CM, int R, int kPairBatch, bool kFull, bool kUnfused>
@@ -728,6 +728,8 @@ __device__ __forceinline__ void flat_batch(const LdsGraph &L, const uint32_t *S,
     for (int r = 0; r < R; ++r) {
         double c[kPairBatch];
         uint32_t l[kPairBatch];
+        double pc[2 * kPairBatch];  // PG-like offers: cost, left set, operator
+        uint32_t pl[2 * kPairBatch], po[2 * kPairBatch];
         double mn = best[r].c;
 #pragma unroll
         for (int u = 0; u < kPairBatch; ++u) {
@@ -760,8 +762,14 @@ __device__ __forceinline__ void flat_batch(const LdsGraph &L, const uint32_t *S,
                     offer_if<CM>(true, one, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
                     if (live) sink.keys[(uint64_t)sink.slot[r] * k + p0 + (uint32_t)u + 1u] = PairKey{one.c, one.l, one.op};
                 } else {
-                    offer_if<CM>(live, best[r].key, hA ? hjA : nlA, A, hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
-                    offer_if<CM>(live, best[r].key, hB ? hjB : nlB, B, hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP);
+                    // both orientations; a slot past the last member offers +inf
+                    pc[2 * u] = live ? (hA ? hjA : nlA) : __builtin_inf();
+                    pl[2 * u] = A;
+                    po[2 * u] = hA ? MPDP_OP_HASH : MPDP_OP_NESTLOOP;
+                    pc[2 * u + 1] = live ? (hB ? hjB : nlB) : __builtin_inf();
+                    pl[2 * u + 1] = B;
+                    po[2 * u + 1] = hB ? MPDP_OP_HASH : MPDP_OP_NESTLOOP;
+                    mn = __builtin_fmin(mn, __builtin_fmin(pc[2 * u], pc[2 * u + 1]));
                 }
             }
         }
@@ -774,6 +782,22 @@ __device__ __forceinline__ void flat_batch(const LdsGraph &L, const uint32_t *S,
             }
             best[r].c = mn;
             best[r].l = nl;
+        }
+        if (CM != MPDP_COST_COUT && !kUnfused) {
+            // PG-like: the smallest cost, then the smallest left set at it;
+            // the left sets of a set's offers all differ (one relation, or
+            // all but one, and both only for two relations, which have one
+            // pair), so that left set names one offer, whose operator is
+            // taken: the key order (cost, left set, operator)
+            uint32_t nl = best[r].c == mn ? best[r].l : ~0u;
+#pragma unroll
+            for (int o = 0; o < 2 * kPairBatch; ++o) nl = min(nl, pc[o] == mn ? pl[o] : ~0u);
+            uint32_t nop = (best[r].c == mn && best[r].l == nl) ? best[r].op : ~0u;
+#pragma unroll
+            for (int o = 0; o < 2 * kPairBatch; ++o) nop = min(nop, (pc[o] == mn && pl[o] == nl) ? po[o] : ~0u);
+            best[r].c = mn;
+            best[r].l = nl;
+            best[r].op = nop;
         }
     }
 }
@@ -823,7 +847,7 @@ __device__ __forceinline__ void eval_flat_sets(const LdsGraph &L, const MemoPtrs
         T[r] = S[r] & ~1u;
         best[r].c = __builtin_inf();
         best[r].l = ~0u;
-        best[r].key = worst_key();
+        best[r].op = ~0u;
         if (kUnfused) sink.keys[(uint64_t)sink.slot[r] * k] = PairKey{~0ull, ~0u, ~0u};  // member 0 has no pair
     }
     const uint32_t np = k - 1;
@@ -842,7 +866,8 @@ __device__ __forceinline__ void eval_flat_sets(const LdsGraph &L, const MemoPtrs
             store_best(M, off_k + pa[r], Key{(unsigned long long)__double_as_longlong(best[r].c), best[r].l,
                                              MPDP_OP_JOIN}, cardS[r]);
         } else {
-            store_best(M, off_k + pa[r], best[r].key, cardS[r]);
+            store_best(M, off_k + pa[r], Key{(unsigned long long)__double_as_longlong(best[r].c), best[r].l,
+                                             best[r].op}, cardS[r]);
         }
     }
 }
