@@ -676,12 +676,14 @@ __device__ __forceinline__ void eval_tree_set(const LdsGraph &L, const MemoPtrs 
 // card(S) is tree_card_n's product with its conditions settled: each member
 // ascending multiplies its card, then its selectivity to relation 0 (1.0
 // for relation 0 itself), and no member has another smaller neighbour.
-// Under C_out a batch's keys are reduced without per-pair branches: the
-// smallest cost of the batch and the running best first, then the smallest
-// left set among the pairs that reach it, which is key_less's order (a
-// connected set has at least one pair, so the running best's +inf start
-// never survives).  Pairs go in batches of kPairBatch (members 1 .. k - 1);
-// only the last batch of a set has slots past its last member.
+// A batch's keys are reduced without per-offer branches: the smallest cost
+// of the batch and the running best first, then the smallest left set among
+// the offers that reach it, which is key_less's order (a connected set has
+// at least one pair, so the running best's +inf start never survives; under
+// PG-like the operator follows from the left set, see flat_batch).  Pairs go
+// in batches of kPairBatch (members 1 .. k - 1); only the last batch of a
+// set has slots past its last member, and they take no part (skipped under
+// C_out, +inf offers under PG-like).
 struct FlatBest {
     double c;     // running smallest cost (+inf before the first pair)
     uint32_t l;   // smallest left set at that cost
